@@ -1,0 +1,119 @@
+/*
+ * goldi.h -- C ABI of the MI355X (gfx950) Poseidon-12 / Goldilocks Merkle
+ * builder.
+ *
+ * What is computed (arXiv 2506.09505):
+ *   - the Goldilocks field p = 2^64 - 2^32 + 1 (Sec. 2.4, Eq. 1); every word
+ *     handed in or out is a canonical element, 0 <= x < p;
+ *   - the Poseidon permutation of a 12-word state: 4 full, 22 partial, 4 full
+ *     rounds with S-box x^7 and a 12 x 12 matrix (Sec. 2.4, Alg. 1);
+ *   - the sponge "absorbing" rows in chunks of eight words (Sec. 2.4): state
+ *     starts at zero, each chunk is added into words 0..7 (a short last chunk
+ *     adds zeros), then the state is permuted; the digest is words 0..3;
+ *   - the Merkle tree (Sec. 2.4 "Merkle Tree", Sec. 4.2): leaf digests first,
+ *     then level by level each parent is the sponge of the 8-word
+ *     concatenation left||right of its two children, until one root.  An
+ *     unpaired last node of a level moves up unchanged.
+ * The round constants and matrix are a seeded instance (the paper prints no
+ * values); the library is compiled against that one instance.
+ *
+ * Layouts (all words are uint64_t):
+ *   states    [n][12] row-major, permuted in place.
+ *   leaves    column-major: element (row r, column c) at leaves[c*n_rows + r]
+ *             (columns are polynomials, rows are the tree's leaves).
+ *   nodes_out level-major, 4 words per node: level 0 (n_rows leaf digests),
+ *             then level 1 (ceil(n_rows/2) nodes), ... ; the root is the last
+ *             node.  Size: goldi_merkle_num_nodes(n_rows) nodes.
+ *
+ * Memory: every data pointer is DEVICE memory (hipMalloc, or a PyTorch
+ * tensor's storage) on the current HIP device.  The caller owns and
+ * allocates every buffer; the library keeps no pointer after a call returns
+ * (synchronous calls) or after the stream work completes (asynchronous
+ * calls).  nodes_out must not overlap leaves.
+ *
+ * Errors: every call returns a status code.  Inputs >= p are detected on the
+ * device and give GOLDI_ENONCANON (output contents are then unspecified).
+ * Null pointers, zero sizes or sizes whose byte counts overflow give
+ * GOLDI_EINVAL before anything is launched.  HIP failures give GOLDI_EDEVICE;
+ * goldi_last_error() returns a thread-local message for the last failure.
+ * No C++ exception crosses this interface.
+ *
+ * Threads: calls are thread-safe.  Synchronous calls run on the legacy null
+ * stream of the current device and return when the work is complete.
+ */
+#ifndef GOLDI_H
+#define GOLDI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GOLDI_OK = 0,
+    GOLDI_EINVAL = -1,    /* bad argument (null, zero size, overflow)        */
+    GOLDI_ENONCANON = -2, /* an input word was >= p                          */
+    GOLDI_EDEVICE = -3,   /* a HIP call failed; see goldi_last_error()       */
+    GOLDI_ENOMEM = -4     /* a device allocation failed                      */
+};
+
+/* Poseidon-12 permutation (Sec. 2.4, Alg. 1) of n states, in place.
+ * states: device pointer to [n][12] words, each < p.  n >= 1.
+ * Returns GOLDI_OK, GOLDI_EINVAL, GOLDI_ENONCANON or GOLDI_EDEVICE. */
+int goldi_poseidon_permute(uint64_t *states, size_t n);
+
+/* Number of nodes of a tree over n leaves: sum of the level sizes n_l with
+ * n_0 = n and n_{l+1} = ceil(n_l / 2) down to 1 (2n - 1 when n is a power of
+ * two).  Returns 0 for n = 0. */
+size_t goldi_merkle_num_nodes(size_t n_rows);
+
+/* Leaf linear hash (the sponge of Sec. 2.4 over each row, Sec. 4.2):
+ * leaves column-major [n_cols][n_rows] -> digests [n_rows][4].
+ * n_rows >= 1, n_cols >= 1.  Same error codes as the permutation. */
+int goldi_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests);
+
+/* Whole Merkle tree (Sec. 2.4 "Merkle Tree", Sec. 4.2): writes every node of
+ * the tree over the rows of `leaves` into nodes_out (level-major, see above).
+ * n_rows >= 1, n_cols >= 1. */
+int goldi_merkle_build(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes_out);
+
+/* One tree for goldi_merkle_build_many. */
+typedef struct {
+    const uint64_t *leaves; /* device, column-major [n_cols][n_rows]          */
+    size_t n_rows;          /* >= 1                                           */
+    size_t n_cols;          /* >= 1                                           */
+    uint64_t *nodes_out;    /* device, goldi_merkle_num_nodes(n_rows) * 4 words */
+} goldi_tree_t;
+
+/* Many independent trees in one call (the trees of Sec. 4.2, built side by
+ * side).  trees: HOST array of n_trees descriptors (n_trees >= 1); each
+ * tree's output equals goldi_merkle_build on that tree alone.  Outputs of
+ * different trees must not overlap each other or any input. */
+int goldi_merkle_build_many(const goldi_tree_t *trees, size_t n_trees);
+
+/* Asynchronous twins.  They enqueue on `stream` (a hipStream_t; 0 = null
+ * stream) and return without waiting.  Argument checks happen before
+ * anything is enqueued; device-side failures are reported by OR-ing a bit
+ * into *dev_status (a device word the caller zeroes beforehand): bit 0 =
+ * an input word was >= p.  The return value covers launch errors only. */
+int goldi_poseidon_permute_async(uint64_t *states, size_t n, uint32_t *dev_status, void *stream);
+int goldi_leaf_hash_async(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests,
+                          uint32_t *dev_status, void *stream);
+int goldi_merkle_build_async(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes_out,
+                             uint32_t *dev_status, void *stream);
+int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
+                                  void *stream);
+
+/* Static text for a status code. */
+const char *goldi_strerror(int code);
+
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char *goldi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GOLDI_H */

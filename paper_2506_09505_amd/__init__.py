@@ -1,0 +1,201 @@
+"""MI355X (gfx950) Poseidon-12 / Goldilocks Merkle builder -- Python binding.
+
+A thin ctypes layer over ``libgoldi.so`` (C ABI in ``include/goldi.h``) with
+the same function names.  It only marshals arguments: every step of the
+permutation, leaf hashing and tree reduction runs in the HIP kernels.
+PyTorch supplies device memory and streams; tensors are ``torch.uint64`` on a
+ROCm device.  If the library is not built, every call raises -- there is no
+CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgoldi.so")
+
+GOLDI_OK, GOLDI_EINVAL, GOLDI_ENONCANON, GOLDI_EDEVICE, GOLDI_ENOMEM = 0, -1, -2, -3, -4
+P = 0xFFFFFFFF00000001
+WIDTH, RATE, DIGEST = 12, 8, 4
+
+# Symbols declared in include/goldi.h.
+EXPORTS = ("goldi_poseidon_permute", "goldi_poseidon_permute_async", "goldi_merkle_num_nodes",
+           "goldi_leaf_hash", "goldi_leaf_hash_async", "goldi_merkle_build", "goldi_merkle_build_async",
+           "goldi_merkle_build_many", "goldi_merkle_build_many_async", "goldi_strerror",
+           "goldi_last_error")
+
+
+class GoldiError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d): %s" % (where, _strerror(code), code, detail))
+
+
+class _Tree(ctypes.Structure):
+    _fields_ = [("leaves", ctypes.c_void_p), ("n_rows", ctypes.c_size_t),
+                ("n_cols", ctypes.c_size_t), ("nodes_out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("%s is missing: build it with `python -m paper_2506_09505_amd.build` "
+                               "(or __graft_entry__.build())" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, ci = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        L.goldi_poseidon_permute.argtypes = [vp, sz]
+        L.goldi_poseidon_permute_async.argtypes = [vp, sz, vp, vp]
+        L.goldi_merkle_num_nodes.argtypes = [sz]
+        L.goldi_merkle_num_nodes.restype = sz
+        L.goldi_leaf_hash.argtypes = [vp, sz, sz, vp]
+        L.goldi_leaf_hash_async.argtypes = [vp, sz, sz, vp, vp, vp]
+        L.goldi_merkle_build.argtypes = [vp, sz, sz, vp]
+        L.goldi_merkle_build_async.argtypes = [vp, sz, sz, vp, vp, vp]
+        L.goldi_merkle_build_many.argtypes = [ctypes.POINTER(_Tree), sz]
+        L.goldi_merkle_build_many_async.argtypes = [ctypes.POINTER(_Tree), sz, vp, vp]
+        L.goldi_strerror.argtypes = [ci]
+        L.goldi_strerror.restype = ctypes.c_char_p
+        L.goldi_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("goldi_merkle_num_nodes", "goldi_strerror", "goldi_last_error"):
+                getattr(L, name).restype = ci
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().goldi_strerror(code).decode()
+    except Exception:  # pragma: no cover
+        return "status"
+
+
+def _check(code: int, where: str):
+    if code != GOLDI_OK:
+        raise GoldiError(code, where, lib().goldi_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_u64(t, what: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint64 or not t.is_cuda:
+        raise TypeError("%s must be a torch.uint64 tensor on a ROCm device" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return t
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def goldi_merkle_num_nodes(n_rows: int) -> int:
+    return lib().goldi_merkle_num_nodes(n_rows)
+
+
+def goldi_poseidon_permute(states):
+    """Permutes ``states`` ([n, 12] uint64, on device) in place."""
+    _dev_u64(states, "states")
+    n = states.numel() // WIDTH
+    if states.numel() != n * WIDTH:
+        raise ValueError("states must hold a multiple of 12 words")
+    with _torch().cuda.device(states.device):
+        _check(lib().goldi_poseidon_permute(states.data_ptr(), n), "goldi_poseidon_permute")
+    return states
+
+
+def goldi_poseidon_permute_async(states, dev_status, stream=None):
+    _dev_u64(states, "states")
+    with _torch().cuda.device(states.device):
+        _check(lib().goldi_poseidon_permute_async(states.data_ptr(), states.numel() // WIDTH,
+                                                  dev_status.data_ptr(), _stream_ptr(stream)),
+               "goldi_poseidon_permute_async")
+    return states
+
+
+def _alloc(n_words: int, like):
+    torch = _torch()
+    return torch.empty(n_words, dtype=torch.uint64, device=like.device)
+
+
+def goldi_leaf_hash(leaves, n_rows: int, n_cols: int, digests=None):
+    """Digests ``[n_rows, 4]`` of the rows of the column-major ``leaves``."""
+    _dev_u64(leaves, "leaves")
+    if digests is None:
+        digests = _alloc(n_rows * DIGEST, leaves).view(n_rows, DIGEST)
+    _dev_u64(digests, "digests")
+    with _torch().cuda.device(leaves.device):
+        _check(lib().goldi_leaf_hash(leaves.data_ptr(), n_rows, n_cols, digests.data_ptr()), "goldi_leaf_hash")
+    return digests
+
+
+def goldi_leaf_hash_async(leaves, n_rows, n_cols, digests, dev_status, stream=None):
+    _dev_u64(leaves, "leaves")
+    _dev_u64(digests, "digests")
+    with _torch().cuda.device(leaves.device):
+        _check(lib().goldi_leaf_hash_async(leaves.data_ptr(), n_rows, n_cols, digests.data_ptr(),
+                                           dev_status.data_ptr(), _stream_ptr(stream)), "goldi_leaf_hash_async")
+    return digests
+
+
+def goldi_merkle_build(leaves, n_rows: int, n_cols: int, nodes_out=None):
+    """Every node (level-major, ``[num_nodes, 4]``) of the tree over the rows
+    of the column-major ``leaves`` (``leaves[c*n_rows + r]``)."""
+    _dev_u64(leaves, "leaves")
+    if nodes_out is None:
+        nodes_out = _alloc(goldi_merkle_num_nodes(n_rows) * DIGEST, leaves).view(-1, DIGEST)
+    _dev_u64(nodes_out, "nodes_out")
+    with _torch().cuda.device(leaves.device):
+        _check(lib().goldi_merkle_build(leaves.data_ptr(), n_rows, n_cols, nodes_out.data_ptr()),
+               "goldi_merkle_build")
+    return nodes_out
+
+
+def goldi_merkle_build_async(leaves, n_rows, n_cols, nodes_out, dev_status, stream=None):
+    _dev_u64(leaves, "leaves")
+    _dev_u64(nodes_out, "nodes_out")
+    with _torch().cuda.device(leaves.device):
+        _check(lib().goldi_merkle_build_async(leaves.data_ptr(), n_rows, n_cols, nodes_out.data_ptr(),
+                                              dev_status.data_ptr(), _stream_ptr(stream)),
+               "goldi_merkle_build_async")
+    return nodes_out
+
+
+def _tree_array(trees):
+    arr = (_Tree * len(trees))()
+    for k, (leaves, n_rows, n_cols, out) in enumerate(trees):
+        _dev_u64(leaves, "leaves")
+        _dev_u64(out, "nodes_out")
+        arr[k] = _Tree(leaves.data_ptr(), n_rows, n_cols, out.data_ptr())
+    return arr
+
+
+def goldi_merkle_build_many(trees, outputs=None):
+    """``trees``: list of ``(leaves, n_rows, n_cols)``; returns the list of node tensors."""
+    if outputs is None:
+        outputs = [_alloc(goldi_merkle_num_nodes(n) * DIGEST, lv).view(-1, DIGEST) for lv, n, _ in trees]
+    arr = _tree_array([(lv, n, w, o) for (lv, n, w), o in zip(trees, outputs)])
+    with _torch().cuda.device(trees[0][0].device):
+        _check(lib().goldi_merkle_build_many(arr, len(trees)), "goldi_merkle_build_many")
+    return outputs
+
+
+def goldi_merkle_build_many_async(trees, outputs, dev_status, stream=None):
+    arr = _tree_array([(lv, n, w, o) for (lv, n, w), o in zip(trees, outputs)])
+    with _torch().cuda.device(trees[0][0].device):
+        _check(lib().goldi_merkle_build_many_async(arr, len(trees), dev_status.data_ptr(), _stream_ptr(stream)),
+               "goldi_merkle_build_many_async")
+    return outputs

@@ -1,0 +1,87 @@
+// Goldilocks field arithmetic on gfx950, on 32-bit limbs.
+//
+// p = 2^64 - 2^32 + 1 (Sec. 2.4, Eq. 1).  An element travels as a uint64_t,
+// i.e. a pair of 32-bit VGPRs (lo, hi).  Inside the permutation values are
+// kept *weakly reduced*: any 64-bit word w stands for w mod p (a word is
+// either x or x + p, because p > 2^63).  Only values leaving the kernel are
+// made canonical (0 <= x < p), which is what the paper requires of its
+// outputs (Sec. 3.2).
+//
+// Products use four 32x32->64 multiply-adds (v_mad_u64_u32), the limb split
+// of the paper's 32-bit-half multiplication (Sec. 3.2, the SVE branch of the
+// mul_128 listing); gfx950 issues them at the full VALU rate, so there is no
+// reason to avoid them.  Reduction of a 128-bit value r = r_hh 2^96 +
+// r_hl 2^64 + r_l uses 2^64 = 2^32 - 1 (mod p) (Sec. 3.1, Eqs. 2-3):
+//     r = r_l + r_hl (2^32 - 1) - r_hh   (mod p),
+// which is the paper's Reduce128 (Alg. 2, with the masks read as the equations
+// state them: r_l = low 64 bits, r_hl = bits 64..95, r_hh = bits 96..127).
+// The multiplication by 2^32 - 1 is one multiply-add with the inline constant
+// -1 instead of a shift and a subtract.
+#pragma once
+#include <stdint.h>
+
+namespace goldi {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+static constexpr u64 P = 0xFFFFFFFF00000001ull;
+static constexpr u64 EPS = 0xFFFFFFFFull;  // 2^64 mod p = 2^32 - 1
+
+__device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
+__device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
+__device__ __forceinline__ u64 mk64(u32 lo, u32 hi) { return ((u64)hi << 32) | lo; }
+
+// a * b + c with 32-bit a, b and 64-bit c: one v_mad_u64_u32.  Never overflows
+// when c < 2^64 - (2^32-1)^2, in particular when c < 2^33.
+__device__ __forceinline__ u64 mad32(u32 a, u32 b, u64 c) { return (u64)a * b + c; }
+
+// Full 128-bit product of two 64-bit words.
+__device__ __forceinline__ void mul_wide(u64 a, u64 b, u64 &lo, u64 &hi) {
+    const u32 a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+    const u64 p00 = mad32(a0, b0, 0);
+    const u64 t = mad32(a0, b1, hi32(p00));   // <= (2^32-1)^2 + 2^32 - 1
+    const u64 u = mad32(a1, b0, lo32(t));     // same bound
+    const u64 v = mad32(a1, b1, hi32(t));     // same bound
+    lo = mk64(lo32(p00), lo32(u));
+    hi = v + hi32(u);                          // the true high word: no overflow
+}
+
+// x + y mod p, weak result, valid when at least one operand is < p
+// (then a wrapped sum is < p and adding 2^32 - 1 cannot wrap again).
+__device__ __forceinline__ u64 add_weak(u64 x, u64 y) {
+    u64 s;
+    const bool c = __builtin_add_overflow(x, y, &s);
+    return s + (c ? EPS : 0);
+}
+
+// 128-bit (hi, lo) -> weak 64-bit word, Alg. 2 / Eq. 3 without the final
+// canonicalisation.
+__device__ __forceinline__ u64 reduce128(u64 lo, u64 hi) {
+    const u32 hl = lo32(hi), hh = hi32(hi);
+    // t = r_l - r_hh; on borrow the wrapped word exceeds the true value by
+    // 2^64 = 2^32 - 1 (mod p), so take 2^32 - 1 back off (cannot wrap again).
+    u64 t;
+    const bool borrow = __builtin_sub_overflow(lo, (u64)hh, &t);
+    t -= borrow ? EPS : 0;
+    // + r_hl (2^32 - 1): at most 2^64 - 2^33 + 1 < p, so add_weak applies.
+    return add_weak(t, mad32(hl, 0xFFFFFFFFu, 0));
+}
+
+__device__ __forceinline__ u64 mul(u64 a, u64 b) {
+    u64 lo, hi;
+    mul_wide(a, b, lo, hi);
+    return reduce128(lo, hi);
+}
+
+__device__ __forceinline__ u64 sqr(u64 a) { return mul(a, a); }
+
+// Weak word -> canonical representative in [0, p): subtract p when x >= p,
+// i.e. when x + (2^32 - 1) carries out of 64 bits.
+__device__ __forceinline__ u64 canon(u64 x) {
+    u64 y;
+    const bool ge = __builtin_add_overflow(x, EPS, &y);
+    return ge ? y : x;
+}
+
+}  // namespace goldi

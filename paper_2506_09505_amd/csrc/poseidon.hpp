@@ -1,0 +1,94 @@
+// Poseidon-12 permutation over Goldilocks, one state per lane, on gfx950.
+//
+// Structure (Sec. 2.4, Alg. 1): a 12-word state, HALF_FULL_ROUNDS = 4 full
+// rounds, PARTIAL_ROUNDS = 22 partial rounds, 4 full rounds; S-box x^7; a
+// 12 x 12 matrix with small entries (Table 1's 8-bit mult_72 / mmult_4x12_8).
+// Round r adds C[r], applies the S-box (to all words in a full round, to word
+// 0 in a partial round) and multiplies by M.  The constant of round r + 1 is
+// folded into the matrix product of round r, so each round costs one pass.
+//
+// Layout: the state lives in 24 VGPRs (12 x (lo, hi)); the matrix entries
+// are inline constants of the multiply-adds; the round constants are read
+// per round with scalar loads from a small constant table (wave-uniform, so
+// they land in SGPRs).  The round loops are not unrolled: one full-round body
+// and one partial-round body keep the code small enough for the instruction
+// cache, which a fully unrolled permutation (~17k instructions) would not.
+//
+// Partial rounds use the dense matrix too.  Alg. 1 instead multiplies by a
+// sparse matrix (MDSPartial) with full-size 64-bit entries.  On gfx950 the
+// 32x32 multiply-add issues at the full VALU rate, and a dense product with
+// 6-bit entries costs 2 multiply-adds per term, so the dense form costs about
+// as much as the sparse one while needing no derived constants.
+#pragma once
+#include "field.hpp"
+#include "poseidon12_constants.inc"
+
+namespace goldi {
+
+static constexpr int WIDTH = 12;
+static constexpr int RATE = 8;
+static constexpr int DIGEST = 4;
+static constexpr int HALF_FULL = 4;
+static constexpr int PARTIAL = 22;
+static constexpr int ROUNDS = 2 * HALF_FULL + PARTIAL;
+
+// Round constants, split into 32-bit halves held in 64-bit words (see the
+// generator); row ROUNDS is zero.
+__constant__ u64 RC_SPLIT[ROUNDS + 1][WIDTH][2] = GOLDI_RC_SPLIT_INIT;
+
+__device__ __forceinline__ u64 sbox(u64 x) {
+    const u64 x2 = sqr(x);
+    const u64 x3 = mul(x2, x);
+    const u64 x4 = sqr(x2);
+    return mul(x4, x3);
+}
+
+// V = a_lo + a_hi 2^32 with a_lo, a_hi < 2^43, reduced to a weak word.
+__device__ __forceinline__ u64 reduce_split(u64 a_lo, u64 a_hi) {
+    const u64 t = a_hi + hi32(a_lo);             // < 2^44
+    const u64 x = mk64(lo32(a_lo), lo32(t));      // V = hi32(t) 2^64 + x
+    return add_weak(x, mad32(hi32(t), 0xFFFFFFFFu, 0));
+}
+
+// s <- M s + C[r1]  (C[ROUNDS] = 0).
+__device__ __forceinline__ void mds_add_rc(u64 s[WIDTH], int r1) {
+    u64 out[WIDTH];
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) {
+        u64 a_lo = RC_SPLIT[r1][i][0];
+        u64 a_hi = RC_SPLIT[r1][i][1];
+#pragma unroll
+        for (int j = 0; j < WIDTH; j++) {
+            a_lo = mad32(GOLDI_MDS[i][j], lo32(s[j]), a_lo);
+            a_hi = mad32(GOLDI_MDS[i][j], hi32(s[j]), a_hi);
+        }
+        out[i] = reduce_split(a_lo, a_hi);
+    }
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = out[i];
+}
+
+__device__ __forceinline__ void full_round(u64 s[WIDTH], int r) {
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
+    mds_add_rc(s, r + 1);
+}
+
+__device__ __forceinline__ void partial_round(u64 s[WIDTH], int r) {
+    s[0] = sbox(s[0]);
+    mds_add_rc(s, r + 1);
+}
+
+// In place; input words must be < 2^64 (any word), output words are weak.
+__device__ __forceinline__ void permute(u64 s[WIDTH]) {
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = add_weak(s[i], mk64(lo32(RC_SPLIT[0][i][0]), lo32(RC_SPLIT[0][i][1])));
+#pragma nounroll
+    for (int r = 0; r < HALF_FULL; r++) full_round(s, r);
+#pragma nounroll
+    for (int r = HALF_FULL; r < HALF_FULL + PARTIAL; r++) partial_round(s, r);
+#pragma nounroll
+    for (int r = HALF_FULL + PARTIAL; r < ROUNDS; r++) full_round(s, r);
+}
+
+}  // namespace goldi

@@ -1,0 +1,60 @@
+"""CPU checks of the C ABI library: it exists, loads, exports every symbol
+include/goldi.h declares, and answers the calls that need no GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_2506_09505_amd as goldi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "goldi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(goldi_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("goldi_poseidon_permute", "goldi_merkle_build", "goldi_merkle_build_many"):
+        assert s in syms
+    assert sorted(goldi.EXPORTS) == syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(goldi.LIB_PATH)
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+
+
+def test_num_nodes_matches_oracle():
+    for n in list(range(0, 70)) + [1 << 22, (1 << 21) + 1, 10**9]:
+        assert goldi.goldi_merkle_num_nodes(n) == (oracle.num_nodes(n) if n else 0)
+
+
+def test_rejections_without_device_work():
+    L = goldi.lib()
+    assert L.goldi_poseidon_permute(None, 0) == goldi.GOLDI_EINVAL
+    assert L.goldi_poseidon_permute(None, 5) == goldi.GOLDI_EINVAL
+    assert L.goldi_merkle_build(None, 0, 8, None) == goldi.GOLDI_EINVAL
+    assert L.goldi_merkle_build(None, 8, 0, None) == goldi.GOLDI_EINVAL
+    assert L.goldi_merkle_build_many(None, 0) == goldi.GOLDI_EINVAL
+    assert b"n" in L.goldi_last_error()
+    assert L.goldi_strerror(goldi.GOLDI_EINVAL) == b"invalid argument"
+
+
+def test_constants_table_is_current():
+    from paper_2506_09505_amd import gen_constants
+    gen_constants.main(check=True)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(goldi, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(goldi, "_lib", None)
+    with pytest.raises(RuntimeError):
+        goldi.lib()
