@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the Poseidon-12 / Goldilocks Merkle build on one MI355X.
+
+One step = one whole Merkle build (leaf hashing with the Poseidon-12 sponge
++ the level-by-level 2-to-1 reduce to the root) of the paper's tree shape
+(Sec. 4.2): 2^22 leaves x 8 Goldilocks words, uniform random (seed 1),
+column-major, every node written.  Inputs are generated on the device before
+the timed region; the timed region holds exactly ``--steps`` builds.
+
+Printed: one JSON line with the headline (permutations per second over the
+whole build), the build time, a roofline entry for the dominant kernel
+(integer multiply-adds per second against the chip's 32-bit multiply-add
+peak, from HIP events recorded on the launch stream during the timed region)
+and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Poseidon-12 perms/s + 2^22-leaf Merkle build ms; batched vs plain, bit-exact"
+
+# Algorithmic work of one permutation, in 32x32->64-bit multiply-adds, for
+# the textbook definition evaluated on 32-bit limbs (schoolbook products):
+#   S-boxes: (8 full rounds x 12 + 22 partial rounds x 1) x 4 field products
+#            x 4 limb products                                  = 1,888
+#   matrix:  30 rounds x 144 entries x 2 limb products (entries < 2^32) = 8,640
+MULADDS_PER_PERM = 1888 + 8640
+# gfx950 peak of that operation: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# v_mad_u64_u32 per lane per cycle (measured full rate on MI355X).
+PEAK_MULADD_PER_S = 256 * 4 * 16 * 2.4e9
+
+WORKLOADS = {
+    # name: (n_rows, n_cols, seed, description)
+    "tree22": (1 << 22, 8, 1, "plain single tree: 2^22 leaves x 8 Goldilocks words, column-major, seed 1; "
+                              "Poseidon-12 sponge leaves + binary 2-to-1 reduce, all 2^23-1 nodes written"),
+    "tree10": (1 << 10, 8, 0, "plain single tree: 2^10 leaves x 8 Goldilocks words, column-major, seed 0"),
+    "wide21": (1 << 21, 256, 2, "wide-row commitment tree: 2^21 rows x 256 Goldilocks words, column-major, "
+                                "seed 2; 32 rate-8 chunks per row, binary reduce"),
+}
+
+
+def perms_per_build(n_rows: int, n_cols: int) -> int:
+    return n_rows * ((n_cols + 7) // 8) + (n_rows - 1)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_09505_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get("%s/%s" % (kernel, workload))
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n_rows: int, n_cols: int, seed: int):
+    """The oracle (plain textbook C, all host threads) on a bounded sample:
+    a 2^18-leaf tree of the same leaf shape (524,287 permutations)."""
+    import oracle
+    from synth.inputs import leaves_colmajor
+    n = 1 << 18
+    lv = leaves_colmajor(n, n_cols, seed=seed)
+    prm = oracle.spec_params()
+    threads = oracle.default_threads()
+    oracle.lib()
+    t0 = time.perf_counter()
+    nodes = oracle.merkle_build(prm, lv, n, n_cols, threads=threads)
+    dt = time.perf_counter() - t0
+    perms = perms_per_build(n, n_cols)
+    return {"value": perms / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
+            "sample": "one 2^18-leaf x %d-word tree (seed %d, %d permutations) built by the oracle "
+                      "in %.2f s" % (n_cols, seed, perms, dt)}, (lv, nodes, n)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tree22", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2506_09505_amd as goldi
+    from synth import fill
+
+    n_rows, n_cols, seed, desc = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    leaves = fill.leaves_colmajor_dev(n_rows, n_cols, seed=seed, device=dev)
+    nodes = torch.empty(goldi.goldi_merkle_num_nodes(n_rows) * 4, dtype=torch.uint64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    perms = perms_per_build(n_rows, n_cols)
+
+    for _ in range(args.warmup):
+        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
+    torch.cuda.synchronize()
+
+    # Timed region: exactly `steps` builds; per-kernel HIP events recorded on
+    # the launch stream by the library.
+    goldi.goldi_profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    goldi.goldi_profile_enable(False)
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+
+    kernels = {}
+    for k in ("leaf_hash", "level"):
+        tot, cnt = goldi.goldi_profile_read(k)
+        kernels[k] = (tot, cnt)
+    if int(status.item()) != 0:
+        print("device status %d: non-canonical input" % int(status.item()), file=sys.stderr)
+        return 1
+
+    # Dominant kernel: the leaf hash (n_rows * ceil(n_cols/8) permutations per launch).
+    leaf_ms_avg = kernels["leaf_hash"][0] / max(1, kernels["leaf_hash"][1])
+    leaf_perms = n_rows * ((n_cols + 7) // 8)
+    achieved = leaf_perms * MULADDS_PER_PERM / (leaf_ms_avg * 1e-3)
+    roofline = {"bound": "alu", "kernel": "k_leaf_hash",
+                "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_MULADD_PER_S / 1e12, 3),
+                "unit": "Tops/s", "frac": round(achieved / PEAK_MULADD_PER_S, 4),
+                "op": "32x32->64-bit multiply-add (v_mad_u64_u32), %d per permutation" % MULADDS_PER_PERM,
+                "kernel_ms": round(leaf_ms_avg, 4),
+                "traffic": traffic_from_profiles("k_leaf_hash", args.workload)}
+
+    out = {
+        "metric": METRIC,
+        "value": perms / (ms_per_step * 1e-3),
+        "unit": "perms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_rows": n_rows, "n_cols": n_cols, "seed": seed,
+                   "perms_per_step": perms, "build_ms": round(ms_per_step, 4),
+                   "wall_ms_per_step": round(wall_ms / args.steps, 4),
+                   "level_kernels_ms_per_step": round(kernels["level"][0] / args.steps, 4),
+                   "leaf_kernel_ms_per_step": round(kernels["leaf_hash"][0] / args.steps, 4)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        base, (lv, want, n_s) = cpu_baseline(n_rows, n_cols, seed)
+        # The same sample on the GPU must agree word for word.
+        got = goldi.goldi_merkle_build(torch.from_numpy(lv.view(np.int64)).to(dev).view(torch.uint64), n_s, n_cols)
+        base["bit_exact_vs_gpu"] = bool((got.view(torch.int64).cpu().numpy().view(np.uint64).reshape(-1, 4)
+                                         == want).all())
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

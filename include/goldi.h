@@ -106,6 +106,17 @@ int goldi_merkle_build_async(const uint64_t *leaves, size_t n_rows, size_t n_col
 int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
                                   void *stream);
 
+/* Per-kernel timing for measurement; off by default.  While enabled, every
+ * kernel the library launches is bracketed by two HIP events recorded on the
+ * stream it is launched on.  Costs a few microseconds per launch. */
+int goldi_profile_enable(int on);
+
+/* Sums the elapsed times of the recorded launches of one kernel kind
+ * ("permute", "leaf_hash", "level"), waiting for them to finish, and forgets
+ * them.  total_ms and count are host pointers; returns GOLDI_EINVAL for nulls
+ * and GOLDI_EDEVICE if an event query fails. */
+int goldi_profile_read(const char *kernel, double *total_ms, size_t *count);
+
 /* Static text for a status code. */
 const char *goldi_strerror(int code);
 

@@ -24,7 +24,7 @@ WIDTH, RATE, DIGEST = 12, 8, 4
 EXPORTS = ("goldi_poseidon_permute", "goldi_poseidon_permute_async", "goldi_merkle_num_nodes",
            "goldi_leaf_hash", "goldi_leaf_hash_async", "goldi_merkle_build", "goldi_merkle_build_async",
            "goldi_merkle_build_many", "goldi_merkle_build_many_async", "goldi_strerror",
-           "goldi_last_error")
+           "goldi_last_error", "goldi_profile_enable", "goldi_profile_read")
 
 
 class GoldiError(RuntimeError):
@@ -63,6 +63,9 @@ def lib():
         L.goldi_strerror.argtypes = [ci]
         L.goldi_strerror.restype = ctypes.c_char_p
         L.goldi_last_error.restype = ctypes.c_char_p
+        L.goldi_profile_enable.argtypes = [ci]
+        L.goldi_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_size_t)]
         for name in EXPORTS:
             if name not in ("goldi_merkle_num_nodes", "goldi_strerror", "goldi_last_error"):
                 getattr(L, name).restype = ci
@@ -199,3 +202,15 @@ def goldi_merkle_build_many_async(trees, outputs, dev_status, stream=None):
         _check(lib().goldi_merkle_build_many_async(arr, len(trees), dev_status.data_ptr(), _stream_ptr(stream)),
                "goldi_merkle_build_many_async")
     return outputs
+
+
+def goldi_profile_enable(on: bool = True) -> None:
+    """Bracket every kernel launch with HIP events on its own stream."""
+    _check(lib().goldi_profile_enable(1 if on else 0), "goldi_profile_enable")
+
+
+def goldi_profile_read(kernel: str):
+    """(total_ms, launches) of the recorded launches of one kernel kind; clears them."""
+    ms, cnt = ctypes.c_double(), ctypes.c_size_t()
+    _check(lib().goldi_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "goldi_profile_read")
+    return ms.value, cnt.value

@@ -55,17 +55,57 @@ __device__ __forceinline__ u64 add_weak(u64 x, u64 y) {
     return s + (c ? EPS : 0);
 }
 
-// 128-bit (hi, lo) -> weak 64-bit word, Alg. 2 / Eq. 3 without the final
-// canonicalisation.
+// Inline assembly below: gfx950 needs two wait states between a VALU
+// instruction that writes a carry into an SGPR pair and a VALU instruction
+// that reads it; the compiler inserts them for its own code but not inside
+// inline assembly, hence the explicit "s_nop 1".  VCC is used as a scratch
+// carry destination and declared clobbered.
+
+// x + h (2^32 - 1)  (mod p) for any 64-bit x and 32-bit h, as a weak word.
+// One multiply-add with carry-out; a carry stands for 2^64 = 2^32 - 1, added
+// back with a second multiply-add that cannot overflow (the wrapped sum is
+// below h (2^32 - 1) <= 2^64 - 2^33 + 1).
+__device__ __forceinline__ u64 mad_eps_fold(u32 h, u64 x) {
+    u64 r, c;
+    u32 t;
+    asm("v_mad_u64_u32 %0, %1, %3, -1, %4\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32 %2, vcc, 0, 0, %1\n\t"
+        "v_mad_u64_u32 %0, vcc, %2, -1, %0"
+        : "=&v"(r), "=&s"(c), "=&v"(t)
+        : "v"(h), "v"(x)
+        : "vcc");
+    return r;
+}
+
+// (x1 2^32 + x0) - h  (mod p) as a weak word.  On a borrow the wrapped word
+// exceeds the true difference by 2^64, so p is added back (mod 2^64), which
+// cannot borrow again (the wrapped word is >= 2^64 - 2^32 + 1).
+__device__ __forceinline__ u64 sub_fold(u32 x0, u32 x1, u32 h) {
+    u32 y0, y1, m;
+    u64 b;
+    asm("v_sub_co_u32 %0, %2, %4, %6\n\t"
+        "s_nop 1\n\t"
+        "v_subb_co_u32 %1, %2, %5, 0, %2\n\t"
+        "s_nop 1\n\t"
+        "v_subb_co_u32 %3, vcc, 0, 0, %2\n\t"
+        "v_addc_co_u32 %0, %2, %0, 0, %2\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32 %1, vcc, %1, %3, %2"
+        : "=&v"(y0), "=&v"(y1), "=&s"(b), "=&v"(m)
+        : "v"(x0), "v"(x1), "v"(h)
+        : "vcc");
+    return mk64(y0, y1);
+}
+
+// 128-bit r = hh 2^96 + hl 2^64 + (l1 2^32 + l0) -> weak word congruent to
+// r_l - r_hh + r_hl (2^32 - 1), Alg. 2 / Eq. 3.
+__device__ __forceinline__ u64 reduce128_parts(u32 l0, u32 l1, u32 hl, u32 hh) {
+    return mad_eps_fold(hl, sub_fold(l0, l1, hh));
+}
+
 __device__ __forceinline__ u64 reduce128(u64 lo, u64 hi) {
-    const u32 hl = lo32(hi), hh = hi32(hi);
-    // t = r_l - r_hh; on borrow the wrapped word exceeds the true value by
-    // 2^64 = 2^32 - 1 (mod p), so take 2^32 - 1 back off (cannot wrap again).
-    u64 t;
-    const bool borrow = __builtin_sub_overflow(lo, (u64)hh, &t);
-    t -= borrow ? EPS : 0;
-    // + r_hl (2^32 - 1): at most 2^64 - 2^33 + 1 < p, so add_weak applies.
-    return add_weak(t, mad32(hl, 0xFFFFFFFFu, 0));
+    return reduce128_parts(lo32(lo), hi32(lo), lo32(hi), hi32(hi));
 }
 
 __device__ __forceinline__ u64 mul(u64 a, u64 b) {

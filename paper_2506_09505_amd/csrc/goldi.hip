@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "goldi.h"
 #include "kernels.hpp"
@@ -87,6 +88,41 @@ int acquire_slot(int *dev_out, DeviceSlot **slot) {
     return GOLDI_OK;
 }
 
+// ------------------------------------------------------------- profiling
+// While enabled, every launch is bracketed by two HIP events recorded on the
+// launch stream; goldi_profile_read() sums their elapsed times per kernel.
+struct ProfRecord {
+    const char *name;
+    hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;
+
+template <class F>
+int timed_launch(const char *name, hipStream_t st, F launch) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        on = g_prof_on;
+    }
+    if (!on) {
+        launch();
+        GOLDI_HIP(hipGetLastError());
+        return GOLDI_OK;
+    }
+    ProfRecord r{name, nullptr, nullptr};
+    GOLDI_HIP(hipEventCreate(&r.start));
+    GOLDI_HIP(hipEventCreate(&r.stop));
+    GOLDI_HIP(hipEventRecord(r.start, st));
+    launch();
+    GOLDI_HIP(hipGetLastError());
+    GOLDI_HIP(hipEventRecord(r.stop, st));
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_prof.push_back(r);
+    return GOLDI_OK;
+}
+
 unsigned grid_for(size_t n) { return (unsigned)((n + goldi::BLOCK - 1) / goldi::BLOCK); }
 
 constexpr size_t kMaxGrid = (size_t)0x7FFFFFFF * goldi::BLOCK;
@@ -94,17 +130,17 @@ constexpr size_t kMaxGrid = (size_t)0x7FFFFFFF * goldi::BLOCK;
 // ---------------------------------------------------------------- launches
 
 int launch_permute(uint64_t *states, size_t n, uint32_t *status, hipStream_t st) {
-    hipLaunchKernelGGL(goldi::k_permute, dim3(grid_for(n)), dim3(goldi::BLOCK), 0, st, states, n, status);
-    GOLDI_HIP(hipGetLastError());
-    return GOLDI_OK;
+    return timed_launch("permute", st, [&] {
+        hipLaunchKernelGGL(goldi::k_permute, dim3(grid_for(n)), dim3(goldi::BLOCK), 0, st, states, n, status);
+    });
 }
 
 int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests, uint32_t *status,
                      hipStream_t st) {
-    hipLaunchKernelGGL(goldi::k_leaf_hash, dim3(grid_for(n_rows)), dim3(goldi::BLOCK), 0, st, leaves, n_rows,
-                       n_cols, digests, status);
-    GOLDI_HIP(hipGetLastError());
-    return GOLDI_OK;
+    return timed_launch("leaf_hash", st, [&] {
+        hipLaunchKernelGGL(goldi::k_leaf_hash, dim3(grid_for(n_rows)), dim3(goldi::BLOCK), 0, st, leaves, n_rows,
+                           n_cols, digests, status);
+    });
 }
 
 int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes, uint32_t *status,
@@ -114,9 +150,11 @@ int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *
     size_t off = 0, n = n_rows;
     while (n > 1) {
         const size_t n_par = (n + 1) / 2;
-        hipLaunchKernelGGL(goldi::k_level, dim3(grid_for(n_par)), dim3(goldi::BLOCK), 0, st,
-                           nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST);
-        GOLDI_HIP(hipGetLastError());
+        rc = timed_launch("level", st, [&] {
+            hipLaunchKernelGGL(goldi::k_level, dim3(grid_for(n_par)), dim3(goldi::BLOCK), 0, st,
+                               nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST);
+        });
+        if (rc) return rc;
         off += n;
         n = n_par;
     }
@@ -204,6 +242,38 @@ const char *goldi_strerror(int code) {
 const char *goldi_last_error(void) { return g_last_error.c_str(); }
 
 size_t goldi_merkle_num_nodes(size_t n_rows) { return num_nodes(n_rows); }
+
+int goldi_profile_enable(int on) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_prof_on = on != 0;
+    return GOLDI_OK;
+}
+
+int goldi_profile_read(const char *kernel, double *total_ms, size_t *count) {
+    if (kernel == nullptr || total_ms == nullptr || count == nullptr)
+        return fail(GOLDI_EINVAL, "goldi_profile_read: null argument");
+    std::vector<ProfRecord> mine;
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        std::vector<ProfRecord> rest;
+        for (auto &r : g_prof) (std::string(r.name) == kernel ? mine : rest).push_back(r);
+        g_prof.swap(rest);
+    }
+    double sum = 0.0;
+    int rc = GOLDI_OK;
+    for (auto &r : mine) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess && rc == GOLDI_OK) rc = fail(GOLDI_EDEVICE, "profile event: %s", hipGetErrorString(e));
+        sum += ms;
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    *total_ms = sum;
+    *count = mine.size();
+    return rc;
+}
 
 int goldi_poseidon_permute_async(uint64_t *states, size_t n, uint32_t *dev_status, void *stream) {
     int rc = validate_permute(states, n);

@@ -43,27 +43,54 @@ __device__ __forceinline__ u64 sbox(u64 x) {
     return mul(x4, x3);
 }
 
-// V = a_lo + a_hi 2^32 with a_lo, a_hi < 2^43, reduced to a weak word.
+// V = a_lo + a_hi 2^32 with a_lo, a_hi < 2^43, reduced to a weak word:
+// V = w2 2^64 + (w1 2^32 + lo32(a_lo)) with w1 = hi32(a_lo) + lo32(a_hi)
+// and w2 = hi32(a_hi) + carry, then 2^64 = 2^32 - 1.
 __device__ __forceinline__ u64 reduce_split(u64 a_lo, u64 a_hi) {
-    const u64 t = a_hi + hi32(a_lo);             // < 2^44
-    const u64 x = mk64(lo32(a_lo), lo32(t));      // V = hi32(t) 2^64 + x
-    return add_weak(x, mad32(hi32(t), 0xFFFFFFFFu, 0));
+    u32 c, junk;
+    const u32 w1 = __builtin_addc(hi32(a_lo), lo32(a_hi), 0u, &c);
+    const u32 w2 = __builtin_addc(hi32(a_hi), 0u, c, &junk);
+    return mad_eps_fold(w2, mk64(lo32(a_lo), w1));
+}
+
+// m * x + acc for a matrix entry m (an inline constant, 1..64) as exactly
+// one v_mad_u64_u32; left to itself the compiler turns some entries (powers
+// of two) into longer shift-and-mask sequences on the 64-bit pair.
+#ifndef GOLDI_MDS_ASM
+#define GOLDI_MDS_ASM 1  // 0: plain C++ for non-powers of two, 2: always plain C++
+#endif
+template <unsigned M>
+__device__ __forceinline__ u64 mad_small(u32 x, u64 acc) {
+    static_assert(M >= 1 && M <= 64, "matrix entries are inline constants");
+    if constexpr (GOLDI_MDS_ASM == 2 || (GOLDI_MDS_ASM == 0 && (M & (M - 1)) != 0)) {
+        return mad32(x, M, acc);
+    } else {
+        u64 r;
+        asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(r) : "v"(x), "i"(M), "v"(acc) : "vcc");
+        return r;
+    }
+}
+
+template <int I, int J>
+__device__ __forceinline__ void mds_term(const u64 s[WIDTH], u64 &a_lo, u64 &a_hi) {
+    a_lo = mad_small<GOLDI_MDS[I][J]>(lo32(s[J]), a_lo);
+    a_hi = mad_small<GOLDI_MDS[I][J]>(hi32(s[J]), a_hi);
+    if constexpr (J + 1 < WIDTH) mds_term<I, J + 1>(s, a_lo, a_hi);
+}
+
+template <int I>
+__device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], int r1) {
+    u64 a_lo = RC_SPLIT[r1][I][0];
+    u64 a_hi = RC_SPLIT[r1][I][1];
+    mds_term<I, 0>(s, a_lo, a_hi);
+    out[I] = reduce_split(a_lo, a_hi);
+    if constexpr (I + 1 < WIDTH) mds_rows<I + 1>(s, out, r1);
 }
 
 // s <- M s + C[r1]  (C[ROUNDS] = 0).
 __device__ __forceinline__ void mds_add_rc(u64 s[WIDTH], int r1) {
     u64 out[WIDTH];
-#pragma unroll
-    for (int i = 0; i < WIDTH; i++) {
-        u64 a_lo = RC_SPLIT[r1][i][0];
-        u64 a_hi = RC_SPLIT[r1][i][1];
-#pragma unroll
-        for (int j = 0; j < WIDTH; j++) {
-            a_lo = mad32(GOLDI_MDS[i][j], lo32(s[j]), a_lo);
-            a_hi = mad32(GOLDI_MDS[i][j], hi32(s[j]), a_hi);
-        }
-        out[i] = reduce_split(a_lo, a_hi);
-    }
+    mds_rows<0>(s, out, r1);
 #pragma unroll
     for (int i = 0; i < WIDTH; i++) s[i] = out[i];
 }
