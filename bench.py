@@ -144,9 +144,8 @@ def main() -> int:
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
 
     kernels = {}
-    for k in ("leaf_hash", "level"):
-        tot, cnt = goldi.goldi_profile_read(k)
-        kernels[k] = (tot, cnt)
+    for k in ("leaf_hash", "leaf_hash_quad", "level", "level_quad"):
+        kernels[k] = goldi.goldi_profile_read(k)
     if int(status.item()) != 0:
         print("device status %d: non-canonical input" % int(status.item()), file=sys.stderr)
         return 1
@@ -179,6 +178,7 @@ def main() -> int:
                    "perms_per_step": perms, "build_ms": round(ms_per_step, 4),
                    "wall_ms_per_step": round(wall_ms / args.steps, 4),
                    "level_kernels_ms_per_step": round(kernels["level"][0] / args.steps, 4),
+                   "level_quad_kernels_ms_per_step": round(kernels["level_quad"][0] / args.steps, 4),
                    "leaf_kernel_ms_per_step": round(kernels["leaf_hash"][0] / args.steps, 4)},
         "roofline": roofline,
     }

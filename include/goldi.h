@@ -106,13 +106,22 @@ int goldi_merkle_build_async(const uint64_t *leaves, size_t n_rows, size_t n_col
 int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
                                   void *stream);
 
+/* Schedule knobs (process-wide).  Every setting computes the same bytes;
+ * only speed changes.  Keys:
+ *   "quad_max_rows"    leaf hashing of at most this many rows runs 4 lanes per
+ *                      row (lower latency, ~25% more instructions per row);
+ *   "quad_max_parents" tree levels of at most this many parents do the same.
+ * Returns GOLDI_EINVAL for an unknown key or a null pointer. */
+int goldi_tune_set(const char *key, size_t value);
+int goldi_tune_get(const char *key, size_t *value);
+
 /* Per-kernel timing for measurement; off by default.  While enabled, every
  * kernel the library launches is bracketed by two HIP events recorded on the
  * stream it is launched on.  Costs a few microseconds per launch. */
 int goldi_profile_enable(int on);
 
 /* Sums the elapsed times of the recorded launches of one kernel kind
- * ("permute", "leaf_hash", "level"), waiting for them to finish, and forgets
+ * ("permute", "leaf_hash", "leaf_hash_quad", "level", "level_quad"), waiting for them to finish, and forgets
  * them.  total_ms and count are host pointers; returns GOLDI_EINVAL for nulls
  * and GOLDI_EDEVICE if an event query fails. */
 int goldi_profile_read(const char *kernel, double *total_ms, size_t *count);

@@ -24,7 +24,8 @@ WIDTH, RATE, DIGEST = 12, 8, 4
 EXPORTS = ("goldi_poseidon_permute", "goldi_poseidon_permute_async", "goldi_merkle_num_nodes",
            "goldi_leaf_hash", "goldi_leaf_hash_async", "goldi_merkle_build", "goldi_merkle_build_async",
            "goldi_merkle_build_many", "goldi_merkle_build_many_async", "goldi_strerror",
-           "goldi_last_error", "goldi_profile_enable", "goldi_profile_read")
+           "goldi_last_error", "goldi_profile_enable", "goldi_profile_read",
+           "goldi_tune_set", "goldi_tune_get")
 
 
 class GoldiError(RuntimeError):
@@ -64,6 +65,8 @@ def lib():
         L.goldi_strerror.restype = ctypes.c_char_p
         L.goldi_last_error.restype = ctypes.c_char_p
         L.goldi_profile_enable.argtypes = [ci]
+        L.goldi_tune_set.argtypes = [ctypes.c_char_p, sz]
+        L.goldi_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]
         L.goldi_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_size_t)]
         for name in EXPORTS:
@@ -214,3 +217,14 @@ def goldi_profile_read(kernel: str):
     ms, cnt = ctypes.c_double(), ctypes.c_size_t()
     _check(lib().goldi_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "goldi_profile_read")
     return ms.value, cnt.value
+
+
+def goldi_tune_set(key: str, value: int) -> None:
+    """Set a schedule knob ("quad_max_rows", "quad_max_parents"); results never change."""
+    _check(lib().goldi_tune_set(key.encode(), value), "goldi_tune_set")
+
+
+def goldi_tune_get(key: str) -> int:
+    v = ctypes.c_size_t()
+    _check(lib().goldi_tune_get(key.encode(), ctypes.byref(v)), "goldi_tune_get")
+    return v.value

@@ -3,9 +3,12 @@
 // status reporting.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <mutex>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -125,7 +128,7 @@ int timed_launch(const char *name, hipStream_t st, F launch) {
 
 unsigned grid_for(size_t n) { return (unsigned)((n + goldi::BLOCK - 1) / goldi::BLOCK); }
 
-constexpr size_t kMaxGrid = (size_t)0x7FFFFFFF * goldi::BLOCK;
+constexpr size_t kMaxGrid = (size_t)0x7FFFFFFF * goldi::BLOCK / 4;  // quad kernels use 4 lanes per item
 
 // ---------------------------------------------------------------- launches
 
@@ -135,11 +138,45 @@ int launch_permute(uint64_t *states, size_t n, uint32_t *status, hipStream_t st)
     });
 }
 
+// Launches at or below these sizes use the 4-lanes-per-state kernels, whose
+// permutation latency is about a third of the one-lane kernels'.  Initial
+// values come from GOLDI_QUAD_MAX_ROWS / GOLDI_QUAD_MAX_PARENTS if set;
+// goldi_tune_set() changes them at run time.
+size_t env_size(const char *name, size_t dflt) {
+    const char *v = getenv(name);
+    if (v == nullptr || *v == 0) return dflt;
+    return (size_t)strtoull(v, nullptr, 0);
+}
+std::atomic<size_t> g_quad_max_rows{env_size("GOLDI_QUAD_MAX_ROWS", (size_t)1 << 14)};
+std::atomic<size_t> g_quad_max_parents{env_size("GOLDI_QUAD_MAX_PARENTS", (size_t)1 << 16)};
+size_t quad_max_rows() { return g_quad_max_rows.load(std::memory_order_relaxed); }
+size_t quad_max_parents() { return g_quad_max_parents.load(std::memory_order_relaxed); }
+
 int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests, uint32_t *status,
                      hipStream_t st) {
+    if (n_rows <= quad_max_rows()) {
+        return timed_launch("leaf_hash_quad", st, [&] {
+            hipLaunchKernelGGL(goldi::k_leaf_hash_quad, dim3(grid_for(4 * n_rows)), dim3(goldi::BLOCK), 0, st,
+                               leaves, n_rows, n_cols, digests, status);
+        });
+    }
     return timed_launch("leaf_hash", st, [&] {
         hipLaunchKernelGGL(goldi::k_leaf_hash, dim3(grid_for(n_rows)), dim3(goldi::BLOCK), 0, st, leaves, n_rows,
                            n_cols, digests, status);
+    });
+}
+
+int launch_level(const uint64_t *child, size_t n_child, uint64_t *parent, hipStream_t st) {
+    const size_t n_par = (n_child + 1) / 2;
+    if (n_par <= quad_max_parents()) {
+        return timed_launch("level_quad", st, [&] {
+            hipLaunchKernelGGL(goldi::k_level_quad, dim3(grid_for(4 * n_par)), dim3(goldi::BLOCK), 0, st, child,
+                               n_child, parent);
+        });
+    }
+    return timed_launch("level", st, [&] {
+        hipLaunchKernelGGL(goldi::k_level, dim3(grid_for(n_par)), dim3(goldi::BLOCK), 0, st, child, n_child,
+                           parent);
     });
 }
 
@@ -149,14 +186,10 @@ int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *
     if (rc) return rc;
     size_t off = 0, n = n_rows;
     while (n > 1) {
-        const size_t n_par = (n + 1) / 2;
-        rc = timed_launch("level", st, [&] {
-            hipLaunchKernelGGL(goldi::k_level, dim3(grid_for(n_par)), dim3(goldi::BLOCK), 0, st,
-                               nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST);
-        });
+        rc = launch_level(nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST, st);
         if (rc) return rc;
         off += n;
-        n = n_par;
+        n = (n + 1) / 2;
     }
     return GOLDI_OK;
 }
@@ -242,6 +275,30 @@ const char *goldi_strerror(int code) {
 const char *goldi_last_error(void) { return g_last_error.c_str(); }
 
 size_t goldi_merkle_num_nodes(size_t n_rows) { return num_nodes(n_rows); }
+
+int goldi_tune_set(const char *key, size_t value) {
+    if (key == nullptr) return fail(GOLDI_EINVAL, "goldi_tune_set: null key");
+    if (strcmp(key, "quad_max_rows") == 0) {
+        g_quad_max_rows.store(value);
+    } else if (strcmp(key, "quad_max_parents") == 0) {
+        g_quad_max_parents.store(value);
+    } else {
+        return fail(GOLDI_EINVAL, "goldi_tune_set: unknown key '%s'", key);
+    }
+    return GOLDI_OK;
+}
+
+int goldi_tune_get(const char *key, size_t *value) {
+    if (key == nullptr || value == nullptr) return fail(GOLDI_EINVAL, "goldi_tune_get: null argument");
+    if (strcmp(key, "quad_max_rows") == 0) {
+        *value = quad_max_rows();
+    } else if (strcmp(key, "quad_max_parents") == 0) {
+        *value = quad_max_parents();
+    } else {
+        return fail(GOLDI_EINVAL, "goldi_tune_get: unknown key '%s'", key);
+    }
+    return GOLDI_OK;
+}
 
 int goldi_profile_enable(int on) {
     std::lock_guard<std::mutex> lock(g_prof_mu);

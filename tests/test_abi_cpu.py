@@ -58,3 +58,12 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(goldi, "_lib", None)
     with pytest.raises(RuntimeError):
         goldi.lib()
+
+
+def test_tune_knobs_cpu():
+    old = goldi.goldi_tune_get("quad_max_rows")
+    goldi.goldi_tune_set("quad_max_rows", 123)
+    assert goldi.goldi_tune_get("quad_max_rows") == 123
+    goldi.goldi_tune_set("quad_max_rows", old)
+    with pytest.raises(goldi.GoldiError):
+        goldi.goldi_tune_set("no_such_knob", 1)

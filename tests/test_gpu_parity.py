@@ -170,3 +170,19 @@ def test_device_generator_matches_host():
     assert (got == leaves_colmajor(n, 1, seed=77, stream=5)).all()
     idx = np.array([0, 1, n - 1])
     assert (got[idx] == words_at(77, 5, idx)).all()
+
+
+@pytest.mark.parametrize("rows,parents", [(0, 0), (1 << 40, 1 << 40), (0, 1 << 40), (1 << 40, 0), (100, 7)])
+def test_schedule_independence(prm, rows, parents):
+    # Every schedule (one lane or four lanes per state, at any cut-over) must
+    # write the same bytes.
+    banner("schedule quad_max_rows=%d quad_max_parents=%d" % (rows, parents))
+    old = (goldi.goldi_tune_get("quad_max_rows"), goldi.goldi_tune_get("quad_max_parents"))
+    try:
+        goldi.goldi_tune_set("quad_max_rows", rows)
+        goldi.goldi_tune_set("quad_max_parents", parents)
+        for n, w in [(1, 8), (3, 9), (200, 8), (1000, 33), (5000, 8)]:
+            check_tree_full(prm, n, w, seed=7 * n + w)
+    finally:
+        goldi.goldi_tune_set("quad_max_rows", old[0])
+        goldi.goldi_tune_set("quad_max_parents", old[1])
