@@ -186,3 +186,31 @@ def test_schedule_independence(prm, rows, parents):
     finally:
         goldi.goldi_tune_set("quad_max_rows", old[0])
         goldi.goldi_tune_set("quad_max_parents", old[1])
+
+
+def test_tree_wide_rows_full_size_sampled(prm):
+    # Wide-row commitment tree: 2^21 rows x 256 columns, column-major (4 GiB),
+    # seed 2; generated on the device; sampled rows and parents checked.
+    import torch
+    from synth import fill
+    from synth.inputs import words_at
+    n, w, seed = 1 << 21, 256, 2
+    banner("tree %dx%d sampled" % (n, w))
+    lv = fill.leaves_colmajor_dev(n, w, seed=seed)
+    nodes_t = goldi.goldi_merkle_build(lv, n, w)
+    del lv
+    torch.cuda.empty_cache()
+    nodes = to_host(nodes_t).reshape(-1, 4)
+    offs, sizes = level_offsets(n)
+    assert nodes.shape[0] == 2 * n - 1 and (nodes < np.uint64(P)).all()
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 254)]))
+    cols = np.arange(w, dtype=np.int64)
+    sub = words_at(seed, 0, (cols[:, None] * n + rows[None, :]).reshape(-1))
+    assert (nodes[rows] == oracle.leaf_hash(prm, sub, rows.size, w)).all()
+    for lvl in range(1, len(sizes)):
+        m = sizes[lvl]
+        idx = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, min(m, 256))]))
+        ch = offs[lvl - 1] + 2 * idx
+        pairs = np.stack([nodes[ch], nodes[ch + 1]], axis=1).reshape(-1, 4)
+        assert (nodes[offs[lvl] + idx] == oracle.merkle_level(prm, pairs)).all(), "level %d" % lvl
