@@ -46,6 +46,9 @@ WORKLOADS = {
     "tree10": (1 << 10, 8, 0, "plain single tree: 2^10 leaves x 8 Goldilocks words, column-major, seed 0"),
     "wide21": (1 << 21, 256, 2, "wide-row commitment tree: 2^21 rows x 256 Goldilocks words, column-major, "
                                 "seed 2; 32 rate-8 chunks per row, binary reduce"),
+    "batch64": (None, None, 3, "batched: 64 trees, rows floor(2^U) with U uniform on [10, 20], widths uniform "
+                               "in {8,16,32,64,128}, uniform Goldilocks words (seed 3); autotuned batched "
+                               "schedule vs 64 plain single-tree launches"),
 }
 
 
@@ -128,6 +131,9 @@ def main() -> int:
     import paper_2506_09505_amd as goldi
     from synth import fill
 
+    if args.workload == "batch64":
+        return bench_batch(args)
+
     n_rows, n_cols, seed, desc = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -204,6 +210,87 @@ def main() -> int:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_batch(args) -> int:
+    """64 trees of uneven shapes: plain (one build after another) vs the
+    batched many-tree build under the autotuned schedule; bit-exact check."""
+    import torch
+
+    import paper_2506_09505_amd as goldi
+    from paper_2506_09505_amd import autotune
+    from synth import fill
+    from synth.inputs import tree_shapes
+
+    _, _, seed, desc = WORKLOADS["batch64"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rows, ws = tree_shapes(seed, 64, 10, 20, (8, 16, 32, 64, 128))
+    trees = [(fill.leaves_colmajor_dev(int(n), int(w), seed=seed, stream=k, device=dev), int(n), int(w))
+             for k, (n, w) in enumerate(zip(rows, ws))]
+    outs = [torch.empty(goldi.goldi_merkle_num_nodes(n) * 4, dtype=torch.uint64, device=dev) for _, n, _ in trees]
+    plain = [torch.empty_like(o) for o in outs]
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    perms = sum(perms_per_build(n, w) for _, n, w in trees)
+    leaf_perms = sum(n * ((w + 7) // 8) for _, n, w in trees)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    def run_plain():
+        for (lv, n, w), o in zip(trees, plain):
+            goldi.goldi_merkle_build_async(lv, n, w, o, status, stream)
+
+    def run_many():
+        goldi.goldi_merkle_build_many_async(trees, outs, status, stream)
+
+    saved = autotune.current()
+    goldi.goldi_tune_set("batch_mode", 0)
+    goldi.goldi_tune_set("graph", 0)
+    plain_ms = timed(run_plain, max(2, args.steps // 4))
+    autotune.apply(saved)
+    default_ms = timed(run_many, max(2, args.steps // 4))
+    cfg, _, _ = autotune.tune(trees, outs, status, cache_path=None)
+    goldi.goldi_profile_enable(True)
+    ms = timed(run_many, args.steps)
+    goldi.goldi_profile_enable(False)
+    leaf_tot, leaf_cnt = goldi.goldi_profile_read("leaf_hash")
+    for k in ("leaf_hash_quad", "level", "level_quad"):
+        goldi.goldi_profile_read(k)
+    exact = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(outs, plain))
+    autotune.apply(saved)
+    if int(status.item()) != 0:
+        print("device status %d" % int(status.item()), file=sys.stderr)
+        return 1
+    leaf_ms = leaf_tot / max(1, leaf_cnt)
+    achieved = leaf_perms * MULADDS_PER_PERM / (leaf_ms * 1e-3)
+    out = {
+        "metric": METRIC, "value": perms / (ms * 1e-3), "unit": "perms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": desc, "trees": 64, "rows_total": int(rows.sum()), "perms_per_step": perms,
+                   "trees_per_s": 64 / (ms * 1e-3), "plain_64_launches_ms": round(plain_ms, 4),
+                   "batched_default_ms": round(default_ms, 4), "batched_tuned_ms": round(ms, 4),
+                   "speedup_vs_plain": round(plain_ms / ms, 3), "tuned_schedule": cfg,
+                   "bit_exact_vs_plain": bool(exact)},
+        "roofline": {"bound": "alu", "kernel": "k_leaf_hash_batch",
+                     "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_MULADD_PER_S / 1e12, 3),
+                     "unit": "Tops/s", "frac": round(achieved / PEAK_MULADD_PER_S, 4),
+                     "op": "32x32->64-bit multiply-add (v_mad_u64_u32), %d per permutation" % MULADDS_PER_PERM,
+                     "kernel_ms": round(leaf_ms, 4), "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if exact else 1
 
 
 if __name__ == "__main__":

@@ -110,7 +110,14 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
  * only speed changes.  Keys:
  *   "quad_max_rows"    leaf hashing of at most this many rows runs 4 lanes per
  *                      row (lower latency, ~25% more instructions per row);
- *   "quad_max_parents" tree levels of at most this many parents do the same.
+ *   "quad_max_parents" tree levels of at most this many parents do the same;
+ *   "batch_mode"       goldi_merkle_build_many: 1 (default) = one launch per
+ *                      tree level across all trees (up to 64 trees per
+ *                      launch, heaviest rows first), 0 = tree after tree;
+ *   "graph"            goldi_merkle_build_many: 1 = capture the launch
+ *                      sequence into a hipGraph, cached per batch description
+ *                      (pointers, sizes, status word, knobs; 16 most recent),
+ *                      and replay it; 0 (default) = launch directly.
  * Returns GOLDI_EINVAL for an unknown key or a null pointer. */
 int goldi_tune_set(const char *key, size_t value);
 int goldi_tune_get(const char *key, size_t *value);

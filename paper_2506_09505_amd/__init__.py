@@ -46,6 +46,10 @@ def lib():
     """The loaded HIP library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # PyTorch bundles its own HIP runtime (same soname as the system one).
+        # Importing it first makes libgoldi.so bind to that runtime, so both
+        # share one device context and torch's pointers are valid here.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("%s is missing: build it with `python -m paper_2506_09505_amd.build` "
                                "(or __graft_entry__.build())" % LIB_PATH)

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -109,6 +110,11 @@ int timed_launch(const char *name, hipStream_t st, F launch) {
         std::lock_guard<std::mutex> lock(g_prof_mu);
         on = g_prof_on;
     }
+    if (on) {  // no event records inside a stream capture
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) on = false;
+        (void)hipGetLastError();
+    }
     if (!on) {
         launch();
         GOLDI_HIP(hipGetLastError());
@@ -149,6 +155,11 @@ size_t env_size(const char *name, size_t dflt) {
 }
 std::atomic<size_t> g_quad_max_rows{env_size("GOLDI_QUAD_MAX_ROWS", (size_t)1 << 14)};
 std::atomic<size_t> g_quad_max_parents{env_size("GOLDI_QUAD_MAX_PARENTS", (size_t)1 << 16)};
+// Batched builds: 1 = one launch per step across all trees (default), 0 = the
+// plain per-tree schedule.  Graphs: 1 = capture the batched launch sequence
+// into a hipGraph cached per batch description and replay it.
+std::atomic<size_t> g_batch_mode{env_size("GOLDI_BATCH_MODE", 1)};
+std::atomic<size_t> g_graph_mode{env_size("GOLDI_GRAPH_MODE", 0)};
 size_t quad_max_rows() { return g_quad_max_rows.load(std::memory_order_relaxed); }
 size_t quad_max_parents() { return g_quad_max_parents.load(std::memory_order_relaxed); }
 
@@ -192,6 +203,173 @@ int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *
         n = (n + 1) / 2;
     }
     return GOLDI_OK;
+}
+
+// ------------------------------------------------------- batched builds
+
+size_t chunks_of(size_t n_cols) { return (n_cols + goldi::RATE - 1) / goldi::RATE; }
+
+// Launches one step of a batch: fills block_begin from per-tree item counts
+// (lanes_per_item = 1 or 4) and launches `kernel`.
+template <class K, class... Extra>
+int launch_batch(const char *name, K kernel, goldi::Batch &b, const size_t *items, int lanes_per_item,
+                 hipStream_t st, Extra... extra) {
+    uint32_t blocks = 0;
+    for (uint32_t t = 0; t < b.n_trees; t++) {
+        b.block_begin[t] = blocks;
+        blocks += (uint32_t)((items[t] * lanes_per_item + goldi::BLOCK - 1) / goldi::BLOCK);
+    }
+    b.block_begin[b.n_trees] = blocks;
+    if (blocks == 0) return GOLDI_OK;
+    return timed_launch(name, st, [&] {
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(goldi::BLOCK), 0, st, b, extra...);
+    });
+}
+
+// All trees of `order` (indices into trees, at most MAX_BATCH), one launch
+// per step: the leaves of every tree, then level 1 of every tree that has
+// one, and so on.  Trees are ordered by per-row cost, heaviest first, so the
+// longest blocks are dispatched first.
+int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, uint32_t *status, hipStream_t st) {
+    const uint32_t nt = (uint32_t)order.size();
+    goldi::Batch b;
+    memset(&b, 0, sizeof b);
+    b.n_trees = nt;
+    size_t items[goldi::MAX_BATCH];
+    size_t total = 0;
+    for (uint32_t k = 0; k < nt; k++) {
+        const goldi_tree_t &T = trees[order[k]];
+        b.t[k] = {T.leaves, T.nodes_out, (uint32_t)T.n_rows, (uint32_t)T.n_cols};
+        items[k] = T.n_rows;
+        total += T.n_rows;
+    }
+    int rc = total <= quad_max_rows()
+                 ? launch_batch("leaf_hash_quad", goldi::k_leaf_hash_quad_batch, b, items, 4, st, status)
+                 : launch_batch("leaf_hash", goldi::k_leaf_hash_batch, b, items, 1, st, status);
+    if (rc) return rc;
+    // Level loop: off[k] = first node of the current child level of tree k.
+    std::vector<size_t> off(nt, 0), n(nt);
+    for (uint32_t k = 0; k < nt; k++) n[k] = trees[order[k]].n_rows;
+    for (;;) {
+        goldi::Batch lb;
+        memset(&lb, 0, sizeof lb);
+        size_t parents = 0;
+        uint32_t m = 0;
+        for (uint32_t k = 0; k < nt; k++) {
+            if (n[k] <= 1) continue;
+            u64 *nodes = trees[order[k]].nodes_out;
+            lb.t[m] = {nodes + off[k] * goldi::DIGEST, nodes + (off[k] + n[k]) * goldi::DIGEST, (uint32_t)n[k], 0};
+            items[m] = (n[k] + 1) / 2;
+            parents += items[m];
+            m++;
+        }
+        if (m == 0) break;
+        lb.n_trees = m;
+        rc = parents <= quad_max_parents()
+                 ? launch_batch("level_quad", goldi::k_level_quad_batch, lb, items, 4, st)
+                 : launch_batch("level", goldi::k_level_batch, lb, items, 1, st);
+        if (rc) return rc;
+        for (uint32_t k = 0; k < nt; k++) {
+            if (n[k] <= 1) continue;
+            off[k] += n[k];
+            n[k] = (n[k] + 1) / 2;
+        }
+    }
+    return GOLDI_OK;
+}
+
+int launch_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
+    if (g_batch_mode.load() == 0) {
+        for (size_t t = 0; t < n_trees; t++) {
+            int rc = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out, status, st);
+            if (rc) return rc;
+        }
+        return GOLDI_OK;
+    }
+    // Trees too large for 32-bit batch descriptors take the plain path.
+    std::vector<size_t> order;
+    for (size_t t = 0; t < n_trees; t++) {
+        if (trees[t].n_rows > 0xFFFFFFFFull || trees[t].n_cols > 0xFFFFFFFFull) {
+            int rc = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out, status, st);
+            if (rc) return rc;
+        } else {
+            order.push_back(t);
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        const size_t ca = chunks_of(trees[a].n_cols), cb = chunks_of(trees[b].n_cols);
+        return ca != cb ? ca > cb : trees[a].n_rows > trees[b].n_rows;
+    });
+    for (size_t g = 0; g < order.size(); g += goldi::MAX_BATCH) {
+        std::vector<size_t> grp(order.begin() + g, order.begin() + std::min(order.size(), g + goldi::MAX_BATCH));
+        int rc = launch_group(trees, grp, status, st);
+        if (rc) return rc;
+    }
+    return GOLDI_OK;
+}
+
+// Graph cache: the launch sequence of a batch, captured once per distinct
+// (device, status word, knobs, tree descriptors) and replayed afterwards.
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // most recently used last
+constexpr size_t kGraphCacheMax = 16;
+hipStream_t g_capture_stream[kMaxDevices] = {};
+
+int launch_many_graph(int dev, const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
+    std::vector<uint64_t> key = {(uint64_t)dev, (uint64_t)(uintptr_t)status, quad_max_rows(), quad_max_parents(),
+                                 g_batch_mode.load()};
+    for (size_t t = 0; t < n_trees; t++) {
+        key.push_back((uint64_t)(uintptr_t)trees[t].leaves);
+        key.push_back(trees[t].n_rows);
+        key.push_back(trees[t].n_cols);
+        key.push_back((uint64_t)(uintptr_t)trees[t].nodes_out);
+    }
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size(); i++) {
+        if (g_graphs[i].key == key) {
+            GraphEntry e = g_graphs[i];
+            g_graphs.erase(g_graphs.begin() + i);
+            g_graphs.push_back(e);
+            GOLDI_HIP(hipGraphLaunch(e.exec, st));
+            return GOLDI_OK;
+        }
+    }
+    if (g_capture_stream[dev] == nullptr) GOLDI_HIP(hipStreamCreateWithFlags(&g_capture_stream[dev], hipStreamNonBlocking));
+    hipStream_t cs = g_capture_stream[dev];
+    GOLDI_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = launch_many(trees, n_trees, status, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(GOLDI_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(GOLDI_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (g_graphs.size() >= kGraphCacheMax) {
+        (void)hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back({key, exec});
+    GOLDI_HIP(hipGraphLaunch(exec, st));
+    return GOLDI_OK;
+}
+
+int enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
+    if (g_graph_mode.load() != 0 && g_batch_mode.load() != 0) {
+        int dev = 0;
+        GOLDI_HIP(hipGetDevice(&dev));
+        if (dev < 0 || dev >= kMaxDevices) return fail(GOLDI_EDEVICE, "device index %d out of range", dev);
+        return launch_many_graph(dev, trees, n_trees, status, st);
+    }
+    return launch_many(trees, n_trees, status, st);
 }
 
 // ------------------------------------------------------------ validation
@@ -282,6 +460,12 @@ int goldi_tune_set(const char *key, size_t value) {
         g_quad_max_rows.store(value);
     } else if (strcmp(key, "quad_max_parents") == 0) {
         g_quad_max_parents.store(value);
+    } else if (strcmp(key, "batch_mode") == 0) {
+        if (value > 1) return fail(GOLDI_EINVAL, "batch_mode must be 0 or 1");
+        g_batch_mode.store(value);
+    } else if (strcmp(key, "graph") == 0) {
+        if (value > 1) return fail(GOLDI_EINVAL, "graph must be 0 or 1");
+        g_graph_mode.store(value);
     } else {
         return fail(GOLDI_EINVAL, "goldi_tune_set: unknown key '%s'", key);
     }
@@ -294,6 +478,10 @@ int goldi_tune_get(const char *key, size_t *value) {
         *value = quad_max_rows();
     } else if (strcmp(key, "quad_max_parents") == 0) {
         *value = quad_max_parents();
+    } else if (strcmp(key, "batch_mode") == 0) {
+        *value = g_batch_mode.load();
+    } else if (strcmp(key, "graph") == 0) {
+        *value = g_graph_mode.load();
     } else {
         return fail(GOLDI_EINVAL, "goldi_tune_get: unknown key '%s'", key);
     }
@@ -402,24 +590,13 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
     if (rc) return rc;
     rc = check_device_range(dev_status, sizeof(uint32_t), "dev_status");
     if (rc) return rc;
-    for (size_t t = 0; t < n_trees; t++) {
-        rc = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out, dev_status,
-                         (hipStream_t)stream);
-        if (rc) return rc;
-    }
-    return GOLDI_OK;
+    return enqueue_many(trees, n_trees, dev_status, (hipStream_t)stream);
 }
 
 int goldi_merkle_build_many(const goldi_tree_t *trees, size_t n_trees) {
     int rc = validate_many(trees, n_trees);
     if (rc) return rc;
-    return run_sync([&](uint32_t *status) {
-        for (size_t t = 0; t < n_trees; t++) {
-            int r = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out, status, 0);
-            if (r) return r;
-        }
-        return (int)GOLDI_OK;
-    });
+    return run_sync([&](uint32_t *status) { return enqueue_many(trees, n_trees, status, 0); });
 }
 
 }  // extern "C"

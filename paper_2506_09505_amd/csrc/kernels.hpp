@@ -31,32 +31,14 @@ __device__ __forceinline__ void store_digest(u64 *dst, const u64 s[WIDTH]) {
     for (int k = 0; k < DIGEST; k++) dst[k] = canon(s[k]);
 }
 
-// Poseidon permutation of n states [n][12], in place.
-__global__ void GOLDI_KERNEL_ATTRS k_permute(u64 *states, size_t n, uint32_t *status) {
-    const size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    u64 *p = states + i * WIDTH;
-    u64 s[WIDTH];
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < WIDTH; k++) {
-        s[k] = p[k];
-        bad |= s[k] >= P;
-    }
-    report(status, bad);
-    permute(s);
-#pragma unroll
-    for (int k = 0; k < WIDTH; k++) p[k] = canon(s[k]);
-}
+// ---------------------------------------------------------------------------
+// Per-item bodies, shared by the single-tree and the batched kernels.
 
-// Leaf linear hash (Sec. 2.4 sponge): row r of the column-major matrix is
-// absorbed in chunks of 8 words; lane r reads leaves[c*n_rows + r], so a
-// wave's loads of one column are contiguous.
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash(const u64 *__restrict__ leaves, size_t n_rows,
-                                                     size_t n_cols, u64 *__restrict__ digests,
-                                                     uint32_t *status) {
-    const size_t r = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (r >= n_rows) return;
+// Leaf linear hash of row r (Sec. 2.4 sponge, Sec. 4.2 leaves): the row of
+// the column-major matrix is absorbed in chunks of 8 words; lane r reads
+// leaves[c*n_rows + r], so a wave's loads of one column are contiguous.
+__device__ __forceinline__ void leaf_row(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+                                         u64 *__restrict__ digests, uint32_t *status, size_t r) {
     u64 s[WIDTH];
 #pragma unroll
     for (int k = 0; k < WIDTH; k++) s[k] = 0;
@@ -76,14 +58,11 @@ __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash(const u64 *__restrict__ leaves, s
     store_digest(digests + r * DIGEST, s);
 }
 
-// One tree level: parent i = sponge(child 2i || child 2i+1); an unpaired last
-// child moves up unchanged (Sec. 2.4 "Merkle Tree", Sec. 4.2).  Children are
+// Parent i of a level: sponge(child 2i || child 2i+1); an unpaired last child
+// moves up unchanged (Sec. 2.4 "Merkle Tree", Sec. 4.2).  Children are
 // canonical digests written by this library.
-__global__ void GOLDI_KERNEL_ATTRS k_level(const u64 *__restrict__ child, size_t n_child,
-                                                 u64 *__restrict__ parent) {
-    const size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-    const size_t n_par = (n_child + 1) / 2;
-    if (i >= n_par) return;
+__device__ __forceinline__ void level_node(const u64 *__restrict__ child, size_t n_child, u64 *__restrict__ parent,
+                                           size_t i) {
     const u64 *c = child + 2 * i * DIGEST;
     if (2 * i + 1 < n_child) {
         u64 s[WIDTH];
@@ -99,20 +78,24 @@ __global__ void GOLDI_KERNEL_ATTRS k_level(const u64 *__restrict__ child, size_t
     }
 }
 
-// ---------------------------------------------------------------------------
-// Quad variants (4 lanes per state, poseidon_quad.hpp) for latency-bound
-// launches: few rows or few parents.  Whole quads share one state, so a quad
-// is either entirely in range or entirely out of range.
+// Quad bodies (4 lanes per state, poseidon_quad.hpp).  A quad is either
+// entirely in range or entirely out of range, so callers may return early
+// per quad; the LDS constant table must be loaded before that.
 
-// Leaf hash, 4 lanes per row: lane q absorbs words 3q..3q+2 of each chunk.
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad(const u64 *__restrict__ leaves, size_t n_rows,
-                                                    size_t n_cols, u64 *__restrict__ digests,
-                                                    uint32_t *status) {
-    __shared__ QuadRc tbl;
-    quad_rc_load(tbl);
-    const size_t r = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
-    const int q = threadIdx.x & 3;
-    if (r >= n_rows) return;
+// Stores the digest from a quad: words 0..2 live in lane 0, word 3 in lane 1.
+__device__ __forceinline__ void store_digest_quad(u64 *d, const u64 w[3], int q) {
+    if (q == 0) {
+        d[0] = canon(w[0]);
+        d[1] = canon(w[1]);
+        d[2] = canon(w[2]);
+    } else if (q == 1) {
+        d[3] = canon(w[0]);
+    }
+}
+
+__device__ __forceinline__ void leaf_row_quad(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+                                              u64 *__restrict__ digests, uint32_t *status, size_t r, int q,
+                                              const QuadRc &tbl) {
     u64 w[3] = {0, 0, 0};
     bool bad = false;
     for (size_t c0 = 0; c0 < n_cols; c0 += RATE) {
@@ -128,25 +111,11 @@ __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad(const u64 *__restrict__ leav
         permute_quad(w, q, tbl);
     }
     report(status, bad);
-    u64 *d = digests + r * DIGEST;
-    if (q == 0) {
-        d[0] = canon(w[0]);
-        d[1] = canon(w[1]);
-        d[2] = canon(w[2]);
-    } else if (q == 1) {
-        d[3] = canon(w[0]);
-    }
+    store_digest_quad(digests + r * DIGEST, w, q);
 }
 
-// One tree level, 4 lanes per parent.
-__global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, size_t n_child,
-                                                u64 *__restrict__ parent) {
-    __shared__ QuadRc tbl;
-    quad_rc_load(tbl);
-    const size_t i = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
-    const int q = threadIdx.x & 3;
-    const size_t n_par = (n_child + 1) / 2;
-    if (i >= n_par) return;
+__device__ __forceinline__ void level_node_quad(const u64 *__restrict__ child, size_t n_child,
+                                                u64 *__restrict__ parent, size_t i, int q, const QuadRc &tbl) {
     const u64 *c = child + 2 * i * DIGEST;
     if (2 * i + 1 < n_child) {
         u64 w[3];
@@ -156,17 +125,117 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, s
             w[k] = idx < 2 * DIGEST ? c[idx] : 0;
         }
         permute_quad(w, q, tbl);
-        u64 *d = parent + i * DIGEST;
-        if (q == 0) {
-            d[0] = canon(w[0]);
-            d[1] = canon(w[1]);
-            d[2] = canon(w[2]);
-        } else if (q == 1) {
-            d[3] = canon(w[0]);
-        }
+        store_digest_quad(parent + i * DIGEST, w, q);
     } else {
         parent[i * DIGEST + q] = c[q];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Single-tree kernels.
+
+// Poseidon permutation of n states [n][12], in place.
+__global__ void GOLDI_KERNEL_ATTRS k_permute(u64 *states, size_t n, uint32_t *status) {
+    const size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    u64 *p = states + i * WIDTH;
+    u64 s[WIDTH];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < WIDTH; k++) {
+        s[k] = p[k];
+        bad |= s[k] >= P;
+    }
+    report(status, bad);
+    permute(s);
+#pragma unroll
+    for (int k = 0; k < WIDTH; k++) p[k] = canon(s[k]);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+                                               u64 *__restrict__ digests, uint32_t *status) {
+    const size_t r = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r < n_rows) leaf_row(leaves, n_rows, n_cols, digests, status, r);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_level(const u64 *__restrict__ child, size_t n_child, u64 *__restrict__ parent) {
+    const size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < (n_child + 1) / 2) level_node(child, n_child, parent, i);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+                                                    u64 *__restrict__ digests, uint32_t *status) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const size_t r = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
+    if (r < n_rows) leaf_row_quad(leaves, n_rows, n_cols, digests, status, r, threadIdx.x & 3, tbl);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, size_t n_child,
+                                                u64 *__restrict__ parent) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const size_t i = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
+    if (i < (n_child + 1) / 2) level_node_quad(child, n_child, parent, i, threadIdx.x & 3, tbl);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: one launch covers one step (the leaves, or one level) of
+// up to MAX_BATCH independent trees.  The trees are described by value in the
+// kernel arguments; block b belongs to the tree t with
+// block_begin[t] <= b < block_begin[t + 1] (binary search over the uniform
+// kernel-argument array, i.e. scalar loads).
+
+static constexpr int MAX_BATCH = 64;
+
+struct BatchTree {
+    const u64 *src;  // leaves (column-major) or the child level
+    u64 *dst;        // digests (level 0) or the parent level
+    uint32_t n;      // rows, or children
+    uint32_t w;      // columns (leaf launches); unused for levels
+};
+
+struct Batch {
+    BatchTree t[MAX_BATCH];
+    uint32_t block_begin[MAX_BATCH + 1];
+    uint32_t n_trees;
+};
+
+__device__ __forceinline__ int batch_tree_of(const Batch &b, uint32_t blk) {
+    int lo = 0, hi = (int)b.n_trees - 1;
+    while (lo < hi) {  // last t with block_begin[t] <= blk
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.block_begin[mid] <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_batch(const Batch b, uint32_t *status) {
+    const int t = batch_tree_of(b, blockIdx.x);
+    const size_t r = (size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x;
+    if (r < b.t[t].n) leaf_row(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad_batch(const Batch b, uint32_t *status) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const int t = batch_tree_of(b, blockIdx.x);
+    const size_t r = ((size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x) >> 2;
+    if (r < b.t[t].n) leaf_row_quad(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r, threadIdx.x & 3, tbl);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_level_batch(const Batch b) {
+    const int t = batch_tree_of(b, blockIdx.x);
+    const size_t i = (size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x;
+    if (i < ((size_t)b.t[t].n + 1) / 2) level_node(b.t[t].src, b.t[t].n, b.t[t].dst, i);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_level_quad_batch(const Batch b) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const int t = batch_tree_of(b, blockIdx.x);
+    const size_t i = ((size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x) >> 2;
+    if (i < ((size_t)b.t[t].n + 1) / 2) level_node_quad(b.t[t].src, b.t[t].n, b.t[t].dst, i, threadIdx.x & 3, tbl);
 }
 
 }  // namespace goldi

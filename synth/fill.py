@@ -27,6 +27,7 @@ def build() -> str:
 def lib():
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (bind to torch's HIP runtime, see paper_2506_09505_amd.lib)
         if not os.path.exists(LIB):
             raise RuntimeError("%s missing: run __graft_entry__.build()" % LIB)
         L = ctypes.CDLL(LIB)
