@@ -214,3 +214,17 @@ def test_tree_wide_rows_full_size_sampled(prm):
         ch = offs[lvl - 1] + 2 * idx
         pairs = np.stack([nodes[ch], nodes[ch + 1]], axis=1).reshape(-1, 4)
         assert (nodes[offs[lvl] + idx] == oracle.merkle_level(prm, pairs)).all(), "level %d" % lvl
+
+
+def test_golden_vectors_on_gpu():
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_vectors.json")))
+    ins = np.array([[int(v) for v in s] for s in g["permute"]["inputs"]], dtype=np.uint64)
+    d = to_dev(ins)
+    goldi.goldi_poseidon_permute(d)
+    assert [[int(v) for v in s] for s in to_host(d).reshape(-1, 12)] == \
+        [[int(v) for v in s] for s in g["permute"]["outputs"]]
+    n, w = 1 << 10, 8
+    nodes = to_host(goldi.goldi_merkle_build(to_dev(leaves_colmajor(n, w, seed=0)), n, w)).reshape(-1, 4)
+    assert [int(v) for v in nodes[-1]] == [int(v) for v in g["tree_1024x8_seed0"]["root"]]

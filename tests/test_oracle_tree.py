@@ -116,3 +116,15 @@ def test_level_function_matches_build(prm):
     assert (nodes[:n] == lvl0).all() and (nodes[n:n + 6] == lvl1).all()
     # last odd node moves up unchanged
     assert (lvl1[5] == lvl0[10]).all()
+
+
+def test_golden_regression(prm):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_vectors.json")))
+    ins = np.array([[int(v) for v in s] for s in g["permute"]["inputs"]], dtype=np.uint64)
+    outs = [[int(v) for v in s] for s in g["permute"]["outputs"]]
+    assert [[int(v) for v in s] for s in oracle.permute(prm, ins)] == outs
+    n, w = 1 << 10, 8
+    nodes = oracle.merkle_build(prm, leaves_colmajor(n, w, seed=0), n, w)
+    assert [int(v) for v in nodes[-1]] == [int(v) for v in g["tree_1024x8_seed0"]["root"]]
