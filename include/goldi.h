@@ -133,6 +133,66 @@ int goldi_profile_enable(int on);
  * and GOLDI_EDEVICE if an event query fails. */
 int goldi_profile_read(const char *kernel, double *total_ms, size_t *count);
 
+/* ---------------------------------------------------------------- serving
+ * A serving loop with continuous batching.  Requests are tree builds (the
+ * tree of goldi_merkle_build).  A scheduler thread admits waiting requests in
+ * arrival order whenever one of `n_slots` slots (each a HIP stream) is free
+ * and the device bytes of all admitted, unreleased requests stay within
+ * `hbm_budget_bytes`; up to `max_group` requests admitted together are built
+ * as one batch.  Slots run concurrently, so newly admitted requests overlap
+ * on the device with those already running.  Per request the server holds,
+ * in device memory from the stream-ordered allocator, a copy of host leaves
+ * (freed when the build completes) and all nodes (kept until released).
+ * The root is returned to the host.  All server calls are thread-safe. */
+typedef struct goldi_server goldi_server;
+
+typedef struct {
+    int status;            /* GOLDI_OK, GOLDI_ENONCANON or GOLDI_EDEVICE       */
+    size_t n_rows, n_cols;
+    uint64_t *nodes;       /* device, level-major nodes; valid until release  */
+    int64_t t_submit_ns;   /* steady-clock times of submission, admission and */
+    int64_t t_admit_ns;    /* completion (completion is observed by polling   */
+    int64_t t_done_ns;     /* every ~20 us)                                    */
+    int group_size;        /* requests built in the same batch                 */
+    uint64_t root[4];      /* canonical root digest                            */
+} goldi_request_info;
+
+/* Creates a server on the current device.  n_slots in 1..64, max_group in
+ * 1..64, budget > 0.  Returns GOLDI_EINVAL or GOLDI_EDEVICE on failure. */
+int goldi_server_create(size_t hbm_budget_bytes, unsigned n_slots, unsigned max_group, goldi_server **out);
+
+/* Queues one request.  Exactly one of leaves_host (host memory, preferably
+ * pinned; it must stay valid until the request completes) and leaves_dev
+ * (device memory on the server's device, valid until completion) is non-null;
+ * both are column-major [n_cols][n_rows].  n_rows, n_cols in 1..2^32-1.
+ * Returns GOLDI_ENOMEM if the request alone exceeds the budget. */
+int goldi_server_submit(goldi_server *s, const uint64_t *leaves_host, const uint64_t *leaves_dev, size_t n_rows,
+                        size_t n_cols, uint64_t *request_id);
+
+/* Blocks until the request completes and fills *info (host pointer). */
+int goldi_server_wait(goldi_server *s, uint64_t id, goldi_request_info *info);
+
+/* Copies a completed, unreleased request's nodes (goldi_merkle_num_nodes(n_rows)
+ * * 4 words) to dst (device or host memory of at least dst_words words).
+ * Blocks until the copy is done. */
+int goldi_server_read_nodes(goldi_server *s, uint64_t id, uint64_t *dst, size_t dst_words);
+
+/* Frees a completed request's nodes and forgets it. */
+int goldi_server_release(goldi_server *s, uint64_t id);
+
+/* Requests admitted, batches formed and the peak of admitted device bytes. */
+int goldi_server_stats(goldi_server *s, size_t *admitted, size_t *groups, size_t *peak_bytes);
+
+/* Finishes every queued request, then frees the server (unreleased nodes too). */
+int goldi_server_destroy(goldi_server *s);
+
+/* The admission rule, exposed so it can be checked without a GPU: with
+ * `inflight_bytes` already admitted, how many requests from the head of the
+ * queue (device bytes pending_bytes[0..n_pending)) are admitted together:
+ * the longest prefix, at most max_group long, whose bytes fit the budget. */
+int goldi_admission_plan(const size_t *pending_bytes, size_t n_pending, size_t budget, size_t inflight_bytes,
+                         size_t max_group, size_t *take);
+
 /* Static text for a status code. */
 const char *goldi_strerror(int code);
 

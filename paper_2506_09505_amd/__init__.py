@@ -25,13 +25,21 @@ EXPORTS = ("goldi_poseidon_permute", "goldi_poseidon_permute_async", "goldi_merk
            "goldi_leaf_hash", "goldi_leaf_hash_async", "goldi_merkle_build", "goldi_merkle_build_async",
            "goldi_merkle_build_many", "goldi_merkle_build_many_async", "goldi_strerror",
            "goldi_last_error", "goldi_profile_enable", "goldi_profile_read",
-           "goldi_tune_set", "goldi_tune_get")
+           "goldi_tune_set", "goldi_tune_get", "goldi_server_create", "goldi_server_submit",
+           "goldi_server_wait", "goldi_server_release", "goldi_server_stats", "goldi_server_destroy",
+           "goldi_admission_plan", "goldi_server_read_nodes")
 
 
 class GoldiError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         self.code = code
         super().__init__("%s failed: %s (%d): %s" % (where, _strerror(code), code, detail))
+
+
+class _ReqInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n_rows", ctypes.c_size_t), ("n_cols", ctypes.c_size_t),
+                ("nodes", ctypes.c_void_p), ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("group_size", ctypes.c_int), ("root", ctypes.c_uint64 * 4)]
 
 
 class _Tree(ctypes.Structure):
@@ -71,6 +79,15 @@ def lib():
         L.goldi_profile_enable.argtypes = [ci]
         L.goldi_tune_set.argtypes = [ctypes.c_char_p, sz]
         L.goldi_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]
+        psz = ctypes.POINTER(ctypes.c_size_t)
+        L.goldi_server_create.argtypes = [sz, ctypes.c_uint, ctypes.c_uint, ctypes.POINTER(vp)]
+        L.goldi_server_submit.argtypes = [vp, vp, vp, sz, sz, ctypes.POINTER(ctypes.c_uint64)]
+        L.goldi_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(_ReqInfo)]
+        L.goldi_server_release.argtypes = [vp, ctypes.c_uint64]
+        L.goldi_server_stats.argtypes = [vp, psz, psz, psz]
+        L.goldi_server_destroy.argtypes = [vp]
+        L.goldi_server_read_nodes.argtypes = [vp, ctypes.c_uint64, vp, sz]
+        L.goldi_admission_plan.argtypes = [psz, sz, sz, sz, sz, psz]
         L.goldi_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_size_t)]
         for name in EXPORTS:
@@ -232,3 +249,92 @@ def goldi_tune_get(key: str) -> int:
     v = ctypes.c_size_t()
     _check(lib().goldi_tune_get(key.encode(), ctypes.byref(v)), "goldi_tune_get")
     return v.value
+
+
+def goldi_admission_plan(pending_bytes, budget: int, inflight_bytes: int, max_group: int) -> int:
+    """How many requests from the head of the queue the server admits together."""
+    arr = (ctypes.c_size_t * max(1, len(pending_bytes)))(*pending_bytes)
+    take = ctypes.c_size_t()
+    _check(lib().goldi_admission_plan(arr, len(pending_bytes), budget, inflight_bytes, max_group,
+                                      ctypes.byref(take)), "goldi_admission_plan")
+    return take.value
+
+
+class GoldiServer:
+    """Serving loop with continuous batching (goldi_server_* in include/goldi.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, n_slots: int = 8, max_group: int = 8):
+        import torch
+        self._device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        _check(lib().goldi_server_create(hbm_budget_bytes, n_slots, max_group, ctypes.byref(h)),
+               "goldi_server_create")
+        self._h = h
+        self._keep = {}   # inputs referenced until their request completes
+
+    def submit(self, leaves, n_rows: int, n_cols: int) -> int:
+        """Queue a build; `leaves` is a uint64 torch tensor (device, or host --
+        pinned for asynchronous copies) or a uint64 numpy array (host)."""
+        import numpy as np
+        rid = ctypes.c_uint64()
+        host = dev = None
+        if isinstance(leaves, np.ndarray):
+            if leaves.dtype != np.uint64 or not leaves.flags.c_contiguous:
+                raise TypeError("host leaves must be a contiguous uint64 array")
+            host = leaves.ctypes.data
+        else:
+            torch = _torch()
+            if leaves.dtype != torch.uint64 or not leaves.is_contiguous():
+                raise TypeError("leaves must be a contiguous torch.uint64 tensor")
+            if leaves.is_cuda:
+                dev = leaves.data_ptr()
+            else:
+                host = leaves.data_ptr()
+        count = leaves.size if isinstance(leaves, np.ndarray) else leaves.numel()
+        if count < n_rows * n_cols:
+            raise ValueError("leaves hold fewer than n_rows * n_cols words")
+        with _torch().cuda.device(self._device):
+            _check(lib().goldi_server_submit(self._h, host, dev, n_rows, n_cols, ctypes.byref(rid)),
+                   "goldi_server_submit")
+        self._keep[rid.value] = leaves
+        return rid.value
+
+    def wait(self, rid: int) -> dict:
+        info = _ReqInfo()
+        _check(lib().goldi_server_wait(self._h, rid, ctypes.byref(info)), "goldi_server_wait")
+        self._keep.pop(rid, None)
+        return {"status": info.status, "n_rows": info.n_rows, "n_cols": info.n_cols, "nodes_ptr": info.nodes,
+                "t_submit_ns": info.t_submit_ns, "t_admit_ns": info.t_admit_ns, "t_done_ns": info.t_done_ns,
+                "group_size": info.group_size, "root": [int(v) for v in info.root]}
+
+    def nodes(self, rid: int):
+        """Copy of a completed, unreleased request's nodes as a [num_nodes, 4]
+        uint64 device tensor."""
+        torch = _torch()
+        info = _ReqInfo()
+        _check(lib().goldi_server_wait(self._h, rid, ctypes.byref(info)), "goldi_server_wait")
+        n = goldi_merkle_num_nodes(info.n_rows) * DIGEST
+        out = torch.empty(n, dtype=torch.uint64, device="cuda:%d" % self._device)
+        _check(lib().goldi_server_read_nodes(self._h, rid, out.data_ptr(), n), "goldi_server_read_nodes")
+        return out.view(-1, DIGEST)
+
+    def release(self, rid: int) -> None:
+        _check(lib().goldi_server_release(self._h, rid), "goldi_server_release")
+
+    def stats(self) -> dict:
+        a, g, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().goldi_server_stats(self._h, ctypes.byref(a), ctypes.byref(g), ctypes.byref(p)),
+               "goldi_server_stats")
+        return {"admitted": a.value, "groups": g.value, "peak_bytes": p.value}
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().goldi_server_destroy(self._h), "goldi_server_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -24,7 +24,7 @@ HIP_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
 
 
 def sources():
-    return [os.path.join(CSRC, "goldi.hip")]
+    return [os.path.join(CSRC, "goldi.hip"), os.path.join(CSRC, "server.hip")]
 
 
 def build(verbose: bool = False) -> str:

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "goldi.h"
+#include "goldi_internal.hpp"
 #include "kernels.hpp"
 
 using goldi::u64;
@@ -436,6 +437,15 @@ int run_sync(F enqueue) {
 }
 
 }  // namespace
+
+int goldi_internal_enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
+                                hipStream_t stream) {
+    return launch_many(trees, n_trees, dev_status, stream);
+}
+
+int goldi_internal_check_device_range(const void *p, size_t bytes, const char *what) {
+    return check_device_range(p, bytes, what);
+}
 
 extern "C" {
 
