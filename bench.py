@@ -46,6 +46,9 @@ WORKLOADS = {
     "tree10": (1 << 10, 8, 0, "plain single tree: 2^10 leaves x 8 Goldilocks words, column-major, seed 0"),
     "wide21": (1 << 21, 256, 2, "wide-row commitment tree: 2^21 rows x 256 Goldilocks words, column-major, "
                                 "seed 2; 32 rate-8 chunks per row, binary reduce"),
+    "serve": (None, None, 4, "served: Poisson stream, mean 200 requests/s, rows floor(2^U) with U uniform on "
+                             "[12, 22], widths uniform in {8,32,64}, uniform Goldilocks words (seed 4), leaves in "
+                             "pinned host memory, 64 GB HBM budget; continuous batching vs one request at a time"),
     "batch64": (None, None, 3, "batched: 64 trees, rows floor(2^U) with U uniform on [10, 20], widths uniform "
                                "in {8,16,32,64,128}, uniform Goldilocks words (seed 3); autotuned batched "
                                "schedule vs 64 plain single-tree launches"),
@@ -105,6 +108,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tree22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=1000, help="serve: measured requests (after 100 warm-up)")
+    ap.add_argument("--serve-input", default="host", choices=("host", "device"),
+                    help="serve: leaves in pinned host memory (copied in by the server) or already in HBM")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (HBM counter "
                          "calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -133,6 +139,8 @@ def main() -> int:
 
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     n_rows, n_cols, seed, desc = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
@@ -291,6 +299,111 @@ def bench_batch(args) -> int:
     }
     print(json.dumps(out), flush=True)
     return 0 if exact else 1
+
+
+def serve_run(srv_args, shapes, arrivals, bufs, warm):
+    """Submits every request at its arrival time; a waiter thread collects
+    results and releases them.  Returns per-request records."""
+    import threading
+
+    import paper_2506_09505_amd as goldi
+
+    out = [None] * len(shapes)
+    with goldi.GoldiServer(*srv_args) as srv:
+        ids = [None] * len(shapes)
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for k in range(len(shapes)):
+                ready.acquire()
+                info = srv.wait(ids[k])
+                srv.release(ids[k])
+                out[k] = info
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.monotonic()
+        for k, ((n, w), t_arr) in enumerate(zip(shapes, arrivals)):
+            delay = t0 + t_arr - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+            ids[k] = srv.submit(bufs[k % len(bufs)][: n * w], n, w)
+            ready.release()
+        th.join()
+        stats = srv.stats()
+    return out, stats
+
+
+def bench_serve(args) -> int:
+    import numpy as np
+    import torch
+
+    import paper_2506_09505_amd as goldi
+    from synth import fill
+    from synth.inputs import poisson_arrivals, tree_shapes
+
+    _, _, seed, desc = WORKLOADS["serve"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    warm, total = 100, 100 + args.requests
+    rows, ws = tree_shapes(seed, total, 12, 22, (8, 32, 64))
+    arrivals = poisson_arrivals(seed, total, 200.0)
+    shapes = [(int(n), int(w)) for n, w in zip(rows, ws)]
+    words = max(n * w for n, w in shapes)
+    # Four distinct pinned host matrices; request k reads the first n*w words
+    # of matrix k mod 4 as its column-major leaves.
+    bufs = []
+    for b in range(4):
+        d = torch.empty(words, dtype=torch.uint64, device=dev)
+        fill.fill_words(d, seed, 100 + b)
+        if args.serve_input == "device":
+            bufs.append(d)
+            continue
+        h = torch.empty(words, dtype=torch.int64, pin_memory=True)
+        h.copy_(d.view(torch.int64))
+        bufs.append(h.view(torch.uint64))
+        del d
+    torch.cuda.synchronize()
+    budget = 64 * 10**9
+    runs = {}
+    for name, srv_args in (("continuous", (budget, 8, 8)), ("one_at_a_time", (budget, 1, 1))):
+        recs, stats = serve_run(srv_args, shapes, arrivals, bufs, warm)
+        m = recs[warm:]
+        lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) / 1e6 for r in m])
+        wait = np.array([(r["t_admit_ns"] - r["t_submit_ns"]) / 1e6 for r in m])
+        span = (max(r["t_done_ns"] for r in m) - min(r["t_submit_ns"] for r in m)) / 1e9
+        perms = sum(perms_per_build(n, w) for n, w in shapes[warm:])
+        runs[name] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                      "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                      "admission_wait_p99_ms": float(np.percentile(wait, 99)),
+                      "trees_per_s": len(m) / span, "perms_per_s": perms / span,
+                      "statuses_ok": all(r["status"] == 0 for r in recs),
+                      "batches": stats["groups"], "requests": stats["admitted"],
+                      "peak_admitted_bytes": stats["peak_bytes"], "roots": [r["root"] for r in recs]}
+    # Every served root must equal the same build done alone.
+    exact = True
+    for k, (n, w) in enumerate(shapes):
+        lv = bufs[k % 4][: n * w].to(dev)
+        alone = goldi.goldi_merkle_build(lv, n, w)[-1].view(torch.int64).cpu().numpy().view(np.uint64)
+        a = [int(v) for v in alone]
+        exact &= runs["continuous"]["roots"][k] == a and runs["one_at_a_time"]["roots"][k] == a
+    for r in runs.values():
+        del r["roots"]
+    c = runs["continuous"]
+    offered = sum(perms_per_build(n, w) for n, w in shapes[warm:]) / (arrivals[-1] - arrivals[warm])
+    out = {
+        "metric": METRIC, "value": c["perms_per_s"], "unit": "perms/s", "n_gpus": 1, "steps": args.requests,
+        "warmup": warm, "ms_per_step": c["mean_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": desc if args.serve_input == "host" else
+                   desc.replace("leaves in pinned host memory", "leaves already in HBM"),
+                   "requests_measured": args.requests, "offered_perms_per_s": offered,
+                   "offered_requests_per_s": 200.0, "hbm_budget_bytes": budget,
+                   "continuous_batching": runs["continuous"], "one_at_a_time": runs["one_at_a_time"],
+                   "bit_exact_roots_vs_alone": bool(exact)},
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if exact and c["statuses_ok"] else 1
 
 
 if __name__ == "__main__":
