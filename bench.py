@@ -155,8 +155,10 @@ def main() -> int:
         goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
     torch.cuda.synchronize()
 
-    # Timed region: exactly `steps` builds; per-kernel HIP events recorded on
-    # the launch stream by the library.
+    # Timed region: exactly `steps` builds.  The library brackets each launch
+    # of the dominant kernel (the leaf hash) with HIP events on the launch
+    # stream; the other kernels run unbracketed.
+    goldi.goldi_profile_select("leaf_hash")
     goldi.goldi_profile_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -169,10 +171,16 @@ def main() -> int:
     wall_ms = (time.perf_counter() - t0) * 1e3
     goldi.goldi_profile_enable(False)
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    kernels = {"leaf_hash": goldi.goldi_profile_read("leaf_hash")}
 
-    kernels = {}
-    for k in ("leaf_hash", "leaf_hash_quad", "level", "level_quad"):
-        kernels[k] = goldi.goldi_profile_read(k)
+    # Untimed breakdown pass: every kernel bracketed (adds a few us per launch).
+    goldi.goldi_profile_select(None)
+    goldi.goldi_profile_enable(True)
+    for _ in range(3):
+        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
+    torch.cuda.synchronize()
+    goldi.goldi_profile_enable(False)
+    breakdown = {k: goldi.goldi_profile_read(k) for k in ("leaf_hash", "leaf_hash_quad", "level", "level_quad")}
     if int(status.item()) != 0:
         print("device status %d: non-canonical input" % int(status.item()), file=sys.stderr)
         return 1
@@ -204,9 +212,8 @@ def main() -> int:
         "config": {"workload": desc, "n_rows": n_rows, "n_cols": n_cols, "seed": seed,
                    "perms_per_step": perms, "build_ms": round(ms_per_step, 4),
                    "wall_ms_per_step": round(wall_ms / args.steps, 4),
-                   "level_kernels_ms_per_step": round(kernels["level"][0] / args.steps, 4),
-                   "level_quad_kernels_ms_per_step": round(kernels["level_quad"][0] / args.steps, 4),
-                   "leaf_kernel_ms_per_step": round(kernels["leaf_hash"][0] / args.steps, 4)},
+                   "breakdown_ms_per_build": {k: round(v[0] / 3, 4) for k, v in breakdown.items()},
+                   "breakdown_launches_per_build": {k: v[1] // 3 for k, v in breakdown.items()}},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
@@ -269,12 +276,12 @@ def bench_batch(args) -> int:
     autotune.apply(saved)
     default_ms = timed(run_many, max(2, args.steps // 4))
     cfg, _, _ = autotune.tune(trees, outs, status, cache_path=None)
+    goldi.goldi_profile_select("leaf_hash")
     goldi.goldi_profile_enable(True)
     ms = timed(run_many, args.steps)
     goldi.goldi_profile_enable(False)
+    goldi.goldi_profile_select(None)
     leaf_tot, leaf_cnt = goldi.goldi_profile_read("leaf_hash")
-    for k in ("leaf_hash_quad", "level", "level_quad"):
-        goldi.goldi_profile_read(k)
     exact = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(outs, plain))
     autotune.apply(saved)
     if int(status.item()) != 0:

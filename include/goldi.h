@@ -127,6 +127,10 @@ int goldi_tune_get(const char *key, size_t *value);
  * stream it is launched on.  Costs a few microseconds per launch. */
 int goldi_profile_enable(int on);
 
+/* Restricts the timing to one kernel kind (names as for goldi_profile_read);
+ * NULL or "" times every kind again. */
+int goldi_profile_select(const char *kernel);
+
 /* Sums the elapsed times of the recorded launches of one kernel kind
  * ("permute", "leaf_hash", "leaf_hash_quad", "level", "level_quad"), waiting for them to finish, and forgets
  * them.  total_ms and count are host pointers; returns GOLDI_EINVAL for nulls

@@ -27,7 +27,7 @@ EXPORTS = ("goldi_poseidon_permute", "goldi_poseidon_permute_async", "goldi_merk
            "goldi_last_error", "goldi_profile_enable", "goldi_profile_read",
            "goldi_tune_set", "goldi_tune_get", "goldi_server_create", "goldi_server_submit",
            "goldi_server_wait", "goldi_server_release", "goldi_server_stats", "goldi_server_destroy",
-           "goldi_admission_plan", "goldi_server_read_nodes")
+           "goldi_admission_plan", "goldi_server_read_nodes", "goldi_profile_select")
 
 
 class GoldiError(RuntimeError):
@@ -77,6 +77,7 @@ def lib():
         L.goldi_strerror.restype = ctypes.c_char_p
         L.goldi_last_error.restype = ctypes.c_char_p
         L.goldi_profile_enable.argtypes = [ci]
+        L.goldi_profile_select.argtypes = [ctypes.c_char_p]
         L.goldi_tune_set.argtypes = [ctypes.c_char_p, sz]
         L.goldi_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]
         psz = ctypes.POINTER(ctypes.c_size_t)
@@ -231,6 +232,11 @@ def goldi_merkle_build_many_async(trees, outputs, dev_status, stream=None):
 def goldi_profile_enable(on: bool = True) -> None:
     """Bracket every kernel launch with HIP events on its own stream."""
     _check(lib().goldi_profile_enable(1 if on else 0), "goldi_profile_enable")
+
+
+def goldi_profile_select(kernel=None) -> None:
+    """Time only one kernel kind (None: all kinds)."""
+    _check(lib().goldi_profile_select(kernel.encode() if kernel else None), "goldi_profile_select")
 
 
 def goldi_profile_read(kernel: str):

@@ -37,14 +37,30 @@ __device__ __forceinline__ u64 mk64(u32 lo, u32 hi) { return ((u64)hi << 32) | l
 __device__ __forceinline__ u64 mad32(u32 a, u32 b, u64 c) { return (u64)a * b + c; }
 
 // Full 128-bit product of two 64-bit words.
+#ifndef GOLDI_MUL_ASM
+#define GOLDI_MUL_ASM 1
+#endif
 __device__ __forceinline__ void mul_wide(u64 a, u64 b, u64 &lo, u64 &hi) {
     const u32 a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+#if GOLDI_MUL_ASM
+    // p00 = a0 b0; t = a1 b0 + hi(p00) (no overflow); u = a0 b1 + t with
+    // carry c (u + c 2^64 = the middle sum); hi = a1 b1 + (hi(u) + c 2^32).
+    const u64 p00 = mad32(a0, b0, 0);
+    const u64 t = mad32(a1, b0, hi32(p00));
+    u64 u, c;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(u), "=s"(c) : "v"(a0), "v"(b1), "v"(t));
+    u32 cw;
+    asm("s_nop 1\n\tv_addc_co_u32 %0, vcc, 0, 0, %1" : "=v"(cw) : "s"(c) : "vcc");
+    lo = mk64(lo32(p00), lo32(u));
+    hi = mad32(a1, b1, mk64(hi32(u), cw));
+#else
     const u64 p00 = mad32(a0, b0, 0);
     const u64 t = mad32(a0, b1, hi32(p00));   // <= (2^32-1)^2 + 2^32 - 1
     const u64 u = mad32(a1, b0, lo32(t));     // same bound
     const u64 v = mad32(a1, b1, hi32(t));     // same bound
     lo = mk64(lo32(p00), lo32(u));
     hi = v + hi32(u);                          // the true high word: no overflow
+#endif
 }
 
 // x + y mod p, weak result, valid when at least one operand is < p

@@ -102,6 +102,7 @@ struct ProfRecord {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+std::string g_prof_only;  // empty: every kernel kind
 std::vector<ProfRecord> g_prof;
 
 template <class F>
@@ -109,7 +110,7 @@ int timed_launch(const char *name, hipStream_t st, F launch) {
     bool on;
     {
         std::lock_guard<std::mutex> lock(g_prof_mu);
-        on = g_prof_on;
+        on = g_prof_on && (g_prof_only.empty() || g_prof_only == name);
     }
     if (on) {  // no event records inside a stream capture
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -501,6 +502,12 @@ int goldi_tune_get(const char *key, size_t *value) {
 int goldi_profile_enable(int on) {
     std::lock_guard<std::mutex> lock(g_prof_mu);
     g_prof_on = on != 0;
+    return GOLDI_OK;
+}
+
+int goldi_profile_select(const char *kernel) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_prof_only = kernel ? kernel : "";
     return GOLDI_OK;
 }
 

@@ -112,7 +112,10 @@ __device__ __forceinline__ void permute(u64 s[WIDTH]) {
     for (int i = 0; i < WIDTH; i++) s[i] = add_weak(s[i], mk64(lo32(RC_SPLIT[0][i][0]), lo32(RC_SPLIT[0][i][1])));
 #pragma nounroll
     for (int r = 0; r < HALF_FULL; r++) full_round(s, r);
-#pragma nounroll
+#ifndef GOLDI_PARTIAL_UNROLL
+#define GOLDI_PARTIAL_UNROLL 2
+#endif
+#pragma unroll GOLDI_PARTIAL_UNROLL
     for (int r = HALF_FULL; r < HALF_FULL + PARTIAL; r++) partial_round(s, r);
 #pragma nounroll
     for (int r = HALF_FULL + PARTIAL; r < ROUNDS; r++) full_round(s, r);
