@@ -71,11 +71,15 @@ __device__ __forceinline__ u64 mad_small(u32 x, u64 acc) {
     }
 }
 
-template <int I, int J>
+// Terms are accumulated for words 1..11 first and word 0 last: in a partial
+// round only word 0 went through the S-box, so the other eleven products can
+// issue while its S-box chain is still running.
+template <int I, int K>
 __device__ __forceinline__ void mds_term(const u64 s[WIDTH], u64 &a_lo, u64 &a_hi) {
+    constexpr int J = (K + 1) % WIDTH;
     a_lo = mad_small<GOLDI_MDS[I][J]>(lo32(s[J]), a_lo);
     a_hi = mad_small<GOLDI_MDS[I][J]>(hi32(s[J]), a_hi);
-    if constexpr (J + 1 < WIDTH) mds_term<I, J + 1>(s, a_lo, a_hi);
+    if constexpr (K + 1 < WIDTH) mds_term<I, K + 1>(s, a_lo, a_hi);
 }
 
 template <int I>

@@ -45,8 +45,10 @@ __device__ __forceinline__ void quad_row_terms(const u64 (&x)[4][3], u64 &a_lo, 
     }
 }
 
-// rc_lane: this lane's 3 round-constant words for round r1, split halves.
-__device__ __forceinline__ void quad_mds_add_rc(u64 w[3], const u64 (*rc_lane)[2]) {
+// Accumulates the 3 rows of this lane (unreduced, split halves) from the
+// quad's 12 words; rc_lane: this lane's 3 round-constant words, split halves.
+__device__ __forceinline__ void quad_mds_accumulate(const u64 w[3], const u64 (*rc_lane)[2], u64 a_lo[3],
+                                                    u64 a_hi[3]) {
     u64 x[4][3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -55,24 +57,48 @@ __device__ __forceinline__ void quad_mds_add_rc(u64 w[3], const u64 (*rc_lane)[2
         x[2][k] = quad_fetch64<2>(w[k]);
         x[3][k] = quad_fetch64<3>(w[k]);
     }
-    u64 a_lo, a_hi;
-    a_lo = rc_lane[0][0];
-    a_hi = rc_lane[0][1];
-    quad_row_terms<0, 0, 0>(x, a_lo, a_hi);
-    w[0] = reduce_split(a_lo, a_hi);
-    a_lo = rc_lane[1][0];
-    a_hi = rc_lane[1][1];
-    quad_row_terms<1, 0, 0>(x, a_lo, a_hi);
-    w[1] = reduce_split(a_lo, a_hi);
-    a_lo = rc_lane[2][0];
-    a_hi = rc_lane[2][1];
-    quad_row_terms<2, 0, 0>(x, a_lo, a_hi);
-    w[2] = reduce_split(a_lo, a_hi);
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        a_lo[r] = rc_lane[r][0];
+        a_hi[r] = rc_lane[r][1];
+    }
+    quad_row_terms<0, 0, 0>(x, a_lo[0], a_hi[0]);
+    quad_row_terms<1, 0, 0>(x, a_lo[1], a_hi[1]);
+    quad_row_terms<2, 0, 0>(x, a_lo[2], a_hi[2]);
+}
+
+__device__ __forceinline__ void quad_mds_add_rc(u64 w[3], const u64 (*rc_lane)[2]) {
+    u64 a_lo[3], a_hi[3];
+    quad_mds_accumulate(w, rc_lane, a_lo, a_hi);
+#pragma unroll
+    for (int r = 0; r < 3; r++) w[r] = reduce_split(a_lo[r], a_hi[r]);
+}
+
+// Partial round, arranged so the matrix product does not wait for the S-box:
+// the product is accumulated with word 0 of the state (held by lane 0) read
+// as zero, while every lane runs the S-box on its own word 0; lane 0's result
+// is then broadcast to the quad and added with this lane's column-0 entries
+// m0[r] = M[3q + r][0].  nz is all-ones in lanes 1..3 and zero in lane 0.
+__device__ __forceinline__ void quad_partial_round(u64 w[3], const u64 (*rc_lane)[2], u32 nz, const u32 m0[3]) {
+    const u64 w0 = w[0];
+    u64 masked[3] = {mk64(lo32(w0) & nz, hi32(w0) & nz), w[1], w[2]};
+    u64 a_lo[3], a_hi[3];
+    quad_mds_accumulate(masked, rc_lane, a_lo, a_hi);
+    const u64 sb = sbox(w0);
+    const u32 s_lo = (u32)__builtin_amdgcn_mov_dpp((int)lo32(sb), 0x00, 0xF, 0xF, false);  // quad_perm [0,0,0,0]
+    const u32 s_hi = (u32)__builtin_amdgcn_mov_dpp((int)hi32(sb), 0x00, 0xF, 0xF, false);
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        a_lo[r] = mad32(m0[r], s_lo, a_lo[r]);
+        a_hi[r] = mad32(m0[r], s_hi, a_hi[r]);
+        w[r] = reduce_split(a_lo[r], a_hi[r]);
+    }
 }
 
 // The round-constant table in LDS: rc[r][i][half], rows 0..ROUNDS.
 struct QuadRc {
     u64 rc[ROUNDS + 1][WIDTH][2];
+    u32 col0[WIDTH];  // column 0 of M: col0[i] = M[i][0]
 };
 
 // Fills the LDS copy of the table; every thread of the block must call it.
@@ -81,6 +107,7 @@ __device__ __forceinline__ void quad_rc_load(QuadRc &t) {
     u64 *dst = &t.rc[0][0][0];
     constexpr int n = (ROUNDS + 1) * WIDTH * 2;
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    if (threadIdx.x < WIDTH) t.col0[threadIdx.x] = GOLDI_MDS[threadIdx.x][0];
     __syncthreads();
 }
 
@@ -98,11 +125,12 @@ __device__ __forceinline__ void permute_quad(u64 w[3], int q, const QuadRc &t) {
         for (int k = 0; k < 3; k++) w[k] = sbox(w[k]);
         quad_mds_add_rc(w, t.rc[r + 1] + 3 * q);
     }
+    const u32 nz = q == 0 ? 0u : 0xFFFFFFFFu;
+    u32 m0[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++) m0[r] = t.col0[3 * q + r];
 #pragma nounroll
-    for (int r = HALF_FULL; r < HALF_FULL + PARTIAL; r++) {
-        if (q == 0) w[0] = sbox(w[0]);
-        quad_mds_add_rc(w, t.rc[r + 1] + 3 * q);
-    }
+    for (int r = HALF_FULL; r < HALF_FULL + PARTIAL; r++) quad_partial_round(w, t.rc[r + 1] + 3 * q, nz, m0);
 #pragma nounroll
     for (int r = HALF_FULL + PARTIAL; r < ROUNDS; r++) {
 #pragma unroll
