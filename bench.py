@@ -49,6 +49,8 @@ WORKLOADS = {
     "serve": (None, None, 4, "served: Poisson stream, mean 200 requests/s, rows floor(2^U) with U uniform on "
                              "[12, 22], widths uniform in {8,32,64}, uniform Goldilocks words (seed 4), leaves in "
                              "pinned host memory, 64 GB HBM budget; continuous batching vs one request at a time"),
+    "functions": (None, None, 0, "the paper's Table-1 basic functions on gfx950: dependent chains per lane, "
+                                 "1M lanes, rate of each function"),
     "batch64": (None, None, 3, "batched: 64 trees, rows floor(2^U) with U uniform on [10, 20], widths uniform "
                                "in {8,16,32,64,128}, uniform Goldilocks words (seed 3); autotuned batched "
                                "schedule vs 64 plain single-tree launches"),
@@ -141,6 +143,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "functions":
+        return bench_functions(args)
 
     n_rows, n_cols, seed, desc = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
@@ -340,6 +344,32 @@ def serve_run(srv_args, shapes, arrivals, bufs, warm):
         th.join()
         stats = srv.stats()
     return out, stats
+
+
+# VALU instructions per call of each function in the timed loops, counted
+# from this repository's own gfx950 code object (hipcc -S of fieldbench.hip).
+FUNCTION_VALU = {"add": 7, "sub": 6, "reduce_128_64": 9, "square_128": 15, "mult_128": 15, "mult_72": 7,
+                 "sbox": 60, "mmult_12x12_small": 365, "mmult_12x12_full": 3227}
+
+
+def bench_functions(args) -> int:
+    import torch
+
+    from paper_2506_09505_amd import fieldbench
+    torch.cuda.set_device(0)
+    rows = {}
+    for name in fieldbench.OPS:
+        iters = 8 if name == "mmult_12x12_full" else 64
+        rate, ms = fieldbench.throughput(name, threads=256 * 4096, iters=iters)
+        instr = FUNCTION_VALU[name]
+        rows[name] = {"ops_per_s": rate, "kernel_ms": round(ms, 4), "valu_per_op": instr,
+                      "valu_instr_per_s_per_lane_slot": rate * instr / PEAK_MULADD_PER_S}
+    out = {"metric": "Table-1 basic functions on gfx950 (ops/s)", "value": rows["mult_128"]["ops_per_s"],
+           "unit": "mult_128/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": rows["mult_128"]["kernel_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": WORKLOADS["functions"][3], "functions": rows}}
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def bench_serve(args) -> int:

@@ -1,0 +1,48 @@
+/*
+ * goldi_fieldbench.h -- the basic functions of the paper's Table 1 (the
+ * Goldilocks field operations and small mat-vecs behind Poseidon, Sec. 3.1-3.2)
+ * as gfx950 device functions, in a separate library libgoldi_fieldbench.so.
+ * Same device code as the Merkle builder (field.hpp / poseidon.hpp).
+ *
+ * All pointers are DEVICE memory owned by the caller.  Inputs must be
+ * canonical (< p) except the 128-bit reduction, which takes any words.
+ */
+#ifndef GOLDI_FIELDBENCH_H
+#define GOLDI_FIELDBENCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GOLDI_FB_ADD = 0,          /* add (Alg. 4)                                  */
+    GOLDI_FB_SUB = 1,          /* sub (Alg. 6)                                  */
+    GOLDI_FB_REDUCE = 2,       /* reduce_128_64: (a 2^64 + b) mod p (Alg. 2)    */
+    GOLDI_FB_SQUARE = 3,       /* square_128                                     */
+    GOLDI_FB_MULT = 4,         /* mult_128                                       */
+    GOLDI_FB_MULT_SMALL = 5,   /* mult_72: a * (b mod 256)                       */
+    GOLDI_FB_SBOX = 6,         /* x^7 (Sec. 2.4)                                  */
+    GOLDI_FB_MMULT_SMALL = 7,  /* 12x12 mat-vec, the instance's small matrix      */
+    GOLDI_FB_MMULT_FULL = 8,   /* 12x12 mat-vec, full 64-bit entries              */
+    GOLDI_FB_COUNT = 9
+};
+
+/* out[i] = op(a[i], b[i]) for i < n (word ops), or out = op(a) on n states of
+ * 12 words (the two mat-vecs; b unused).  Outputs canonical.  Synchronous.
+ * Returns 0, -1 for bad arguments, -3 for a HIP error. */
+int goldi_fb_eval(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t n);
+
+/* Runs `threads` lanes (a multiple of 256), each applying the function `iters`
+ * times in dependent chains (8 independent words per lane for word ops, one
+ * 12-word state for the mat-vecs), after one warm-up launch; *ms (host) is
+ * the kernel time.  seed: 2 device words; out: `threads` device words. */
+int goldi_fb_throughput(int op, const uint64_t *seed, uint64_t *out, size_t threads, int iters, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GOLDI_FIELDBENCH_H */

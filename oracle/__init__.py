@@ -61,6 +61,7 @@ def lib():
         L.oracle_reduce128.restype = u64
         L.oracle_reduce128.argtypes = [u64, u64]
         L.oracle_permute.argtypes = [ptr, ptr, sz, i32]
+        L.oracle_field_array.argtypes = [i32, ptr, ptr, ptr, sz]
         L.oracle_leaf_hash.argtypes = [ptr, ptr, sz, sz, ptr, i32]
         L.oracle_merkle_level.argtypes = [ptr, ptr, sz, ptr, i32]
         L.oracle_merkle_build.argtypes = [ptr, ptr, sz, sz, ptr, i32]
@@ -114,6 +115,18 @@ def fsub(a, b): return lib().oracle_fsub(a, b)
 def fmul(a, b): return lib().oracle_fmul(a, b)
 def fpow(a, e): return lib().oracle_fpow(a, e)
 def reduce128(hi, lo): return lib().oracle_reduce128(hi, lo)
+
+
+FIELD_OPS = {"add": 0, "sub": 1, "reduce_128_64": 2, "square_128": 3, "mult_128": 4, "mult_72": 5, "sbox": 6}
+
+
+def field_array(name: str, a, b=None) -> np.ndarray:
+    """Element-wise field operation (plain definitions), see oracle_field_array."""
+    a = _u64(a).reshape(-1)
+    b = a if b is None else _u64(b).reshape(-1)
+    out = np.zeros_like(a)
+    lib().oracle_field_array(FIELD_OPS[name], a.ctypes.data, b.ctypes.data, out.ctypes.data, a.size)
+    return out
 
 
 def permute(params: Params, states, threads: int | None = None) -> np.ndarray:

@@ -82,6 +82,24 @@ uint64_t oracle_fpow(uint64_t a, uint64_t e) {
     return r;
 }
 
+/* Element-wise field operations on arrays (for checking the device field
+ * layer): op 0 a+b, 1 a-b, 2 (a 2^64 + b) mod p, 3 a^2, 4 a*b,
+ * 5 a*(b mod 256), 6 a^7.  Each is the plain definition above. */
+void oracle_field_array(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, size_t n) {
+    for (size_t i = 0; i < n; i++) {
+        switch (op) {
+            case 0: out[i] = oracle_fadd(a[i], b[i]); break;
+            case 1: out[i] = oracle_fsub(a[i], b[i]); break;
+            case 2: out[i] = oracle_reduce128(a[i], b[i]); break;
+            case 3: out[i] = oracle_fmul(a[i], a[i]); break;
+            case 4: out[i] = oracle_fmul(a[i], b[i]); break;
+            case 5: out[i] = oracle_fmul(a[i], b[i] & 0xFF); break;
+            case 6: out[i] = oracle_fpow(a[i], 7); break;
+            default: out[i] = 0;
+        }
+    }
+}
+
 /* ---------------------------------------------------------- permutation -- */
 
 static uint64_t sbox(uint64_t x) { return oracle_fpow(x, 7); }

@@ -83,3 +83,18 @@ def test_fermat_inverse_and_sbox_bijection():
         assert oracle.fmul(a, oracle.fpow(a, P - 2)) == 1
         assert oracle.fpow(oracle.fpow(a, 7), d) == a
     assert oracle.fpow(0, 7) == 0 and oracle.fpow(1, 7) == 1 and oracle.fpow(P - 1, 7) == P - 1
+
+
+def test_field_array_matches_scalar_definitions():
+    import numpy as np
+    rnd = random.Random(3)
+    a = np.array([rnd.randrange(P) for _ in range(500)] + EDGE, dtype=np.uint64)
+    b = np.array([rnd.randrange(P) for _ in range(500)] + EDGE[::-1], dtype=np.uint64)
+    ai, bi = [int(v) for v in a], [int(v) for v in b]
+    assert [int(v) for v in oracle.field_array("add", a, b)] == [(x + y) % P for x, y in zip(ai, bi)]
+    assert [int(v) for v in oracle.field_array("sub", a, b)] == [(x - y) % P for x, y in zip(ai, bi)]
+    assert [int(v) for v in oracle.field_array("reduce_128_64", a, b)] == [((x << 64) | y) % P for x, y in zip(ai, bi)]
+    assert [int(v) for v in oracle.field_array("square_128", a)] == [x * x % P for x in ai]
+    assert [int(v) for v in oracle.field_array("mult_128", a, b)] == [x * y % P for x, y in zip(ai, bi)]
+    assert [int(v) for v in oracle.field_array("mult_72", a, b)] == [x * (y & 255) % P for x, y in zip(ai, bi)]
+    assert [int(v) for v in oracle.field_array("sbox", a)] == [pow(x, 7, P) for x in ai]
