@@ -162,7 +162,8 @@ def main() -> int:
     # Timed region: exactly `steps` builds.  The library brackets each launch
     # of the dominant kernel (the leaf hash) with HIP events on the launch
     # stream; the other kernels run unbracketed.
-    leaf_kind = "leaf_hash_quad" if n_rows <= goldi.goldi_tune_get("quad_max_rows") else "leaf_hash"
+    leaf_kind = ("leaf_hash_lane12" if n_rows <= goldi.goldi_tune_get("lane12_max_rows") else
+                 "leaf_hash_quad" if n_rows <= goldi.goldi_tune_get("quad_max_rows") else "leaf_hash")
     goldi.goldi_profile_select(leaf_kind)
     goldi.goldi_profile_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -185,7 +186,8 @@ def main() -> int:
         goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
     torch.cuda.synchronize()
     goldi.goldi_profile_enable(False)
-    breakdown = {k: goldi.goldi_profile_read(k) for k in ("leaf_hash", "leaf_hash_quad", "level", "level_quad")}
+    breakdown = {k: goldi.goldi_profile_read(k) for k in ("leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level",
+                                                          "level_quad", "level_lane12")}
     if int(status.item()) != 0:
         print("device status %d: non-canonical input" % int(status.item()), file=sys.stderr)
         return 1

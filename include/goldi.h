@@ -111,6 +111,10 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
  *   "quad_max_rows"    leaf hashing of at most this many rows runs 4 lanes per
  *                      row (lower latency, ~25% more instructions per row);
  *   "quad_max_parents" tree levels of at most this many parents do the same;
+ *   "lane12_max_rows", "lane12_max_parents"
+ *                      at or below these sizes one state word per lane (a
+ *                      16-lane row per state) is used instead: lower latency
+ *                      again, more instructions in total;
  *   "batch_mode"       goldi_merkle_build_many: 1 (default) = one launch per
  *                      tree level across all trees (up to 64 trees per
  *                      launch, heaviest rows first), 0 = tree after tree;
@@ -132,7 +136,8 @@ int goldi_profile_enable(int on);
 int goldi_profile_select(const char *kernel);
 
 /* Sums the elapsed times of the recorded launches of one kernel kind
- * ("permute", "leaf_hash", "leaf_hash_quad", "level", "level_quad"), waiting for them to finish, and forgets
+ * ("permute", "leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level",
+ * "level_quad", "level_lane12"), waiting for them to finish, and forgets
  * them.  total_ms and count are host pointers; returns GOLDI_EINVAL for nulls
  * and GOLDI_EDEVICE if an event query fails. */
 int goldi_profile_read(const char *kernel, double *total_ms, size_t *count);

@@ -7,9 +7,9 @@ with the real kernels on the real inputs and keeps the fastest:
 * ``batch_mode``: one launch per level across all trees, or tree after tree;
 * ``graph``: replay a captured hipGraph of the launch sequence, or launch
   directly;
-* ``quad_max_rows`` / ``quad_max_parents``: where leaf hashing and tree levels
-  switch from one lane per state (throughput) to four lanes per state
-  (latency).
+* ``quad_max_rows`` / ``quad_max_parents`` and ``lane12_max_rows`` /
+  ``lane12_max_parents``: where leaf hashing and tree levels switch from one
+  lane per state (throughput) to four, then twelve lanes per state (latency).
 
 Results are cached per *shape signature* -- the sorted multiset of
 (row-count octave, chunks per row) of the batch -- in a JSON file, so batches
@@ -26,7 +26,7 @@ import threading
 
 from . import goldi_merkle_build_many_async, goldi_tune_get, goldi_tune_set
 
-KNOBS = ("batch_mode", "graph", "quad_max_rows", "quad_max_parents")
+KNOBS = ("batch_mode", "graph", "quad_max_rows", "quad_max_parents", "lane12_max_rows", "lane12_max_parents")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "goldi_autotune.json")
 
 _lock = threading.Lock()
@@ -40,10 +40,10 @@ def signature(shapes) -> str:
 
 def candidates():
     for bm, gr in ((0, 0), (1, 0), (1, 1)):
-        for qr, qp in itertools.product((1 << 12, 1 << 14, 1 << 16), (1 << 14, 1 << 16, 1 << 17)):
-            if bm == 0 and gr == 1:
-                continue
-            yield {"batch_mode": bm, "graph": gr, "quad_max_rows": qr, "quad_max_parents": qp}
+        for qr, qp in itertools.product((1 << 14, 1 << 16), (1 << 16, 1 << 17)):
+            for l12 in (1 << 10, 1 << 12):
+                yield {"batch_mode": bm, "graph": gr, "quad_max_rows": qr, "quad_max_parents": qp,
+                       "lane12_max_rows": l12, "lane12_max_parents": l12}
 
 
 def current():

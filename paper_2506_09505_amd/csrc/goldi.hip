@@ -136,7 +136,7 @@ int timed_launch(const char *name, hipStream_t st, F launch) {
 
 unsigned grid_for(size_t n) { return (unsigned)((n + goldi::BLOCK - 1) / goldi::BLOCK); }
 
-constexpr size_t kMaxGrid = (size_t)0x7FFFFFFF * goldi::BLOCK / 4;  // quad kernels use 4 lanes per item
+constexpr size_t kMaxGrid = (size_t)0x7FFFFFFF * goldi::BLOCK / 16;  // up to 16 lanes per item
 
 // ---------------------------------------------------------------- launches
 
@@ -162,11 +162,23 @@ std::atomic<size_t> g_quad_max_parents{env_size("GOLDI_QUAD_MAX_PARENTS", (size_
 // into a hipGraph cached per batch description and replay it.
 std::atomic<size_t> g_batch_mode{env_size("GOLDI_BATCH_MODE", 1)};
 std::atomic<size_t> g_graph_mode{env_size("GOLDI_GRAPH_MODE", 0)};
+// At or below these sizes the one-word-per-lane kernels run instead (lower
+// latency still, more instructions in total).
+std::atomic<size_t> g_l12_max_rows{env_size("GOLDI_LANE12_MAX_ROWS", (size_t)1 << 12)};
+std::atomic<size_t> g_l12_max_parents{env_size("GOLDI_LANE12_MAX_PARENTS", (size_t)1 << 12)};
+size_t l12_max_rows() { return g_l12_max_rows.load(std::memory_order_relaxed); }
+size_t l12_max_parents() { return g_l12_max_parents.load(std::memory_order_relaxed); }
 size_t quad_max_rows() { return g_quad_max_rows.load(std::memory_order_relaxed); }
 size_t quad_max_parents() { return g_quad_max_parents.load(std::memory_order_relaxed); }
 
 int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests, uint32_t *status,
                      hipStream_t st) {
+    if (n_rows <= l12_max_rows()) {
+        return timed_launch("leaf_hash_lane12", st, [&] {
+            hipLaunchKernelGGL(goldi::k_leaf_hash_lane12, dim3(grid_for(16 * n_rows)), dim3(goldi::BLOCK), 0, st,
+                               leaves, n_rows, n_cols, digests, status);
+        });
+    }
     if (n_rows <= quad_max_rows()) {
         return timed_launch("leaf_hash_quad", st, [&] {
             hipLaunchKernelGGL(goldi::k_leaf_hash_quad, dim3(grid_for(4 * n_rows)), dim3(goldi::BLOCK), 0, st,
@@ -181,6 +193,12 @@ int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint6
 
 int launch_level(const uint64_t *child, size_t n_child, uint64_t *parent, hipStream_t st) {
     const size_t n_par = (n_child + 1) / 2;
+    if (n_par <= l12_max_parents()) {
+        return timed_launch("level_lane12", st, [&] {
+            hipLaunchKernelGGL(goldi::k_level_lane12, dim3(grid_for(16 * n_par)), dim3(goldi::BLOCK), 0, st, child,
+                               n_child, parent);
+        });
+    }
     if (n_par <= quad_max_parents()) {
         return timed_launch("level_quad", st, [&] {
             hipLaunchKernelGGL(goldi::k_level_quad, dim3(grid_for(4 * n_par)), dim3(goldi::BLOCK), 0, st, child,
@@ -245,7 +263,9 @@ int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, ui
         items[k] = T.n_rows;
         total += T.n_rows;
     }
-    int rc = total <= quad_max_rows()
+    int rc = total <= l12_max_rows()
+                 ? launch_batch("leaf_hash_lane12", goldi::k_leaf_hash_lane12_batch, b, items, 16, st, status)
+             : total <= quad_max_rows()
                  ? launch_batch("leaf_hash_quad", goldi::k_leaf_hash_quad_batch, b, items, 4, st, status)
                  : launch_batch("leaf_hash", goldi::k_leaf_hash_batch, b, items, 1, st, status);
     if (rc) return rc;
@@ -267,7 +287,9 @@ int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, ui
         }
         if (m == 0) break;
         lb.n_trees = m;
-        rc = parents <= quad_max_parents()
+        rc = parents <= l12_max_parents()
+                 ? launch_batch("level_lane12", goldi::k_level_lane12_batch, lb, items, 16, st)
+             : parents <= quad_max_parents()
                  ? launch_batch("level_quad", goldi::k_level_quad_batch, lb, items, 4, st)
                  : launch_batch("level", goldi::k_level_batch, lb, items, 1, st);
         if (rc) return rc;
@@ -322,7 +344,8 @@ constexpr size_t kGraphCacheMax = 16;
 hipStream_t g_capture_stream[kMaxDevices] = {};
 
 int launch_many_graph(int dev, const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
-    std::vector<uint64_t> key = {(uint64_t)dev, (uint64_t)(uintptr_t)status, quad_max_rows(), quad_max_parents(),
+    std::vector<uint64_t> key = {(uint64_t)dev,          (uint64_t)(uintptr_t)status, quad_max_rows(),
+                                 quad_max_parents(),   l12_max_rows(),                l12_max_parents(),
                                  g_batch_mode.load()};
     for (size_t t = 0; t < n_trees; t++) {
         key.push_back((uint64_t)(uintptr_t)trees[t].leaves);
@@ -471,6 +494,10 @@ int goldi_tune_set(const char *key, size_t value) {
         g_quad_max_rows.store(value);
     } else if (strcmp(key, "quad_max_parents") == 0) {
         g_quad_max_parents.store(value);
+    } else if (strcmp(key, "lane12_max_rows") == 0) {
+        g_l12_max_rows.store(value);
+    } else if (strcmp(key, "lane12_max_parents") == 0) {
+        g_l12_max_parents.store(value);
     } else if (strcmp(key, "batch_mode") == 0) {
         if (value > 1) return fail(GOLDI_EINVAL, "batch_mode must be 0 or 1");
         g_batch_mode.store(value);
@@ -489,6 +516,10 @@ int goldi_tune_get(const char *key, size_t *value) {
         *value = quad_max_rows();
     } else if (strcmp(key, "quad_max_parents") == 0) {
         *value = quad_max_parents();
+    } else if (strcmp(key, "lane12_max_rows") == 0) {
+        *value = l12_max_rows();
+    } else if (strcmp(key, "lane12_max_parents") == 0) {
+        *value = l12_max_parents();
     } else if (strcmp(key, "batch_mode") == 0) {
         *value = g_batch_mode.load();
     } else if (strcmp(key, "graph") == 0) {

@@ -6,6 +6,7 @@
 
 #include "poseidon.hpp"
 #include "poseidon_quad.hpp"
+#include "poseidon_lane12.hpp"
 
 namespace goldi {
 
@@ -131,6 +132,39 @@ __device__ __forceinline__ void level_node_quad(const u64 *__restrict__ child, s
     }
 }
 
+// One-word-per-lane bodies (poseidon_lane12.hpp): a 16-lane row per state.
+// Every lane must reach the permutation (it reads other lanes), so range
+// checks guard only loads and stores.
+
+__device__ __forceinline__ void leaf_row_lane12(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+                                                u64 *__restrict__ digests, uint32_t *status, size_t r, bool valid,
+                                                const Lane12 &L, const QuadRc &tbl) {
+    u64 x = 0;
+    bool bad = false;
+    for (size_t c0 = 0; c0 < n_cols; c0 += RATE) {
+        if (valid && L.i < RATE && c0 + L.i < n_cols) {
+            const u64 v = leaves[(c0 + L.i) * n_rows + r];
+            bad |= v >= P;
+            x = add_weak(x, v);
+        }
+        x = permute_lane12(x, L, tbl);
+    }
+    report(status, bad);
+    if (valid && L.i < DIGEST) digests[r * DIGEST + L.i] = canon(x);
+}
+
+__device__ __forceinline__ void level_node_lane12(const u64 *__restrict__ child, size_t n_child,
+                                                  u64 *__restrict__ parent, size_t i, bool valid, const Lane12 &L,
+                                                  const QuadRc &tbl) {
+    const bool pair = valid && 2 * i + 1 < n_child;
+    u64 x = (pair && L.i < 2 * DIGEST) ? child[2 * i * DIGEST + L.i] : 0;
+    x = permute_lane12(x, L, tbl);
+    if (L.i < DIGEST) {
+        if (pair) parent[i * DIGEST + L.i] = canon(x);
+        else if (valid) parent[i * DIGEST + L.i] = child[2 * i * DIGEST + L.i];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Single-tree kernels.
 
@@ -177,6 +211,26 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, s
     quad_rc_load(tbl);
     const size_t i = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
     if (i < (n_child + 1) / 2) level_node_quad(child, n_child, parent, i, threadIdx.x & 3, tbl);
+}
+
+static constexpr int LANE12_PER_BLOCK = BLOCK / 16;  // states per block
+
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+                                                      u64 *__restrict__ digests, uint32_t *status) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const Lane12 L = lane12_setup(tbl);
+    const size_t r = (size_t)blockIdx.x * LANE12_PER_BLOCK + (threadIdx.x >> 4);
+    leaf_row_lane12(leaves, n_rows, n_cols, digests, status, r, r < n_rows && L.i < WIDTH, L, tbl);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_level_lane12(const u64 *__restrict__ child, size_t n_child,
+                                                  u64 *__restrict__ parent) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const Lane12 L = lane12_setup(tbl);
+    const size_t i = (size_t)blockIdx.x * LANE12_PER_BLOCK + (threadIdx.x >> 4);
+    level_node_lane12(child, n_child, parent, i, i < (n_child + 1) / 2 && L.i < WIDTH, L, tbl);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,6 +290,24 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_quad_batch(const Batch b) {
     const int t = batch_tree_of(b, blockIdx.x);
     const size_t i = ((size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x) >> 2;
     if (i < ((size_t)b.t[t].n + 1) / 2) level_node_quad(b.t[t].src, b.t[t].n, b.t[t].dst, i, threadIdx.x & 3, tbl);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12_batch(const Batch b, uint32_t *status) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const Lane12 L = lane12_setup(tbl);
+    const int t = batch_tree_of(b, blockIdx.x);
+    const size_t r = (size_t)(blockIdx.x - b.block_begin[t]) * LANE12_PER_BLOCK + (threadIdx.x >> 4);
+    leaf_row_lane12(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r, r < b.t[t].n && L.i < WIDTH, L, tbl);
+}
+
+__global__ void GOLDI_KERNEL_ATTRS k_level_lane12_batch(const Batch b) {
+    __shared__ QuadRc tbl;
+    quad_rc_load(tbl);
+    const Lane12 L = lane12_setup(tbl);
+    const int t = batch_tree_of(b, blockIdx.x);
+    const size_t i = (size_t)(blockIdx.x - b.block_begin[t]) * LANE12_PER_BLOCK + (threadIdx.x >> 4);
+    level_node_lane12(b.t[t].src, b.t[t].n, b.t[t].dst, i, i < ((size_t)b.t[t].n + 1) / 2 && L.i < WIDTH, L, tbl);
 }
 
 }  // namespace goldi

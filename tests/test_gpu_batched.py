@@ -21,7 +21,7 @@ def prm():
 
 @pytest.fixture
 def knobs():
-    keys = ("batch_mode", "graph", "quad_max_rows", "quad_max_parents")
+    keys = ("batch_mode", "graph", "quad_max_rows", "quad_max_parents", "lane12_max_rows", "lane12_max_parents")
     old = {k: goldi.goldi_tune_get(k) for k in keys}
     yield goldi.goldi_tune_set
     for k, v in old.items():
@@ -65,9 +65,12 @@ def test_quad_cutovers_in_batches(prm, knobs):
     batch = small_batch(13, 9)
     trees = [(to_dev(lv), n, w) for n, w, lv in batch]
     want = [oracle.merkle_build(prm, lv, n, w) for n, w, lv in batch]
-    for rows, parents in [(0, 0), (1 << 40, 1 << 40), (50, 3000)]:
+    for rows, parents, l12r, l12p in [(0, 0, 0, 0), (1 << 40, 1 << 40, 0, 0), (50, 3000, 0, 0),
+                                      (0, 0, 1 << 40, 1 << 40), (1 << 40, 1 << 40, 20, 700)]:
         knobs("quad_max_rows", rows)
         knobs("quad_max_parents", parents)
+        knobs("lane12_max_rows", l12r)
+        knobs("lane12_max_parents", l12p)
         outs = goldi.goldi_merkle_build_many(trees)
         for o, w_ in zip(outs, want):
             assert (to_host(o).reshape(-1, 4) == w_).all()

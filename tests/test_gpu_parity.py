@@ -172,20 +172,26 @@ def test_device_generator_matches_host():
     assert (got[idx] == words_at(77, 5, idx)).all()
 
 
-@pytest.mark.parametrize("rows,parents", [(0, 0), (1 << 40, 1 << 40), (0, 1 << 40), (1 << 40, 0), (100, 7)])
-def test_schedule_independence(prm, rows, parents):
-    # Every schedule (one lane or four lanes per state, at any cut-over) must
-    # write the same bytes.
-    banner("schedule quad_max_rows=%d quad_max_parents=%d" % (rows, parents))
-    old = (goldi.goldi_tune_get("quad_max_rows"), goldi.goldi_tune_get("quad_max_parents"))
+BIG = 1 << 40
+
+
+@pytest.mark.parametrize("rows,parents,l12_rows,l12_parents", [
+    (0, 0, 0, 0), (BIG, BIG, 0, 0), (0, BIG, 0, 0), (BIG, 0, 0, 0), (100, 7, 0, 0),
+    (0, 0, BIG, BIG), (BIG, BIG, 3, 300), (0, 0, 0, BIG), (0, 0, BIG, 0), (5000, 5000, 64, 17)])
+def test_schedule_independence(prm, rows, parents, l12_rows, l12_parents):
+    # Every schedule (one, four or twelve lanes per state, at any cut-over)
+    # must write the same bytes.
+    banner("schedule quad %d/%d lane12 %d/%d" % (rows, parents, l12_rows, l12_parents))
+    keys = ("quad_max_rows", "quad_max_parents", "lane12_max_rows", "lane12_max_parents")
+    old = [goldi.goldi_tune_get(k) for k in keys]
     try:
-        goldi.goldi_tune_set("quad_max_rows", rows)
-        goldi.goldi_tune_set("quad_max_parents", parents)
+        for k, v in zip(keys, (rows, parents, l12_rows, l12_parents)):
+            goldi.goldi_tune_set(k, v)
         for n, w in [(1, 8), (3, 9), (200, 8), (1000, 33), (5000, 8)]:
             check_tree_full(prm, n, w, seed=7 * n + w)
     finally:
-        goldi.goldi_tune_set("quad_max_rows", old[0])
-        goldi.goldi_tune_set("quad_max_parents", old[1])
+        for k, v in zip(keys, old):
+            goldi.goldi_tune_set(k, v)
 
 
 def test_tree_wide_rows_full_size_sampled(prm):
