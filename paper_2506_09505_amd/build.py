@@ -31,6 +31,7 @@ def sources():
 def build(verbose: bool = False) -> str:
     from . import gen_constants
     gen_constants.main()
+    os.makedirs(os.path.join(HERE, "_special"), exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + sources() + ["-o", tmp]
     if verbose:
@@ -45,7 +46,22 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, FB_LIB)
+    # Test-only libraries compiled against special instances with closed forms.
+    for inc in gen_constants.write_specials():
+        name = os.path.basename(inc)[len("special_"):-len(".inc")]
+        out = special_lib(name)
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                                     '-DGOLDI_CONSTANTS_INC="%s"' % os.path.basename(inc)] + sources() + ["-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, out)
     return LIB
+
+
+def special_lib(name: str) -> str:
+    return os.path.join(HERE, "_special", "libgoldi_%s.so" % name)
 
 
 if __name__ == "__main__":

@@ -21,7 +21,11 @@
 // as much as the sparse one while needing no derived constants.
 #pragma once
 #include "field.hpp"
+#ifdef GOLDI_CONSTANTS_INC
+#include GOLDI_CONSTANTS_INC  // a special instance for closed-form tests
+#else
 #include "poseidon12_constants.inc"
+#endif
 
 namespace goldi {
 
@@ -61,8 +65,10 @@ __device__ __forceinline__ u64 reduce_split(u64 a_lo, u64 a_hi) {
 #endif
 template <unsigned M>
 __device__ __forceinline__ u64 mad_small(u32 x, u64 acc) {
-    static_assert(M >= 1 && M <= 64, "matrix entries are inline constants");
-    if constexpr (GOLDI_MDS_ASM == 2 || (GOLDI_MDS_ASM == 0 && (M & (M - 1)) != 0)) {
+    static_assert(M <= 64, "matrix entries are inline constants");
+    if constexpr (M == 0) {
+        return acc;
+    } else if constexpr (GOLDI_MDS_ASM == 2 || (GOLDI_MDS_ASM == 0 && (M & (M - 1)) != 0)) {
         return mad32(x, M, acc);
     } else {
         u64 r;
