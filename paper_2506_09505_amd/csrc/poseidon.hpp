@@ -77,6 +77,21 @@ __device__ __forceinline__ u64 mad_small(u32 x, u64 acc) {
     }
 }
 
+// The same with the accumulator in a scalar register pair: the first term of
+// a row adds the round constant straight from the SGPRs it was loaded into
+// (a VOP3 operand may be scalar), instead of copying it to VGPRs first.
+template <unsigned M>
+__device__ __forceinline__ u64 mad_small_sacc(u32 x, u64 acc) {
+    static_assert(M <= 64, "matrix entries are inline constants");
+    if constexpr (M == 0 || GOLDI_MDS_ASM != 1) {
+        return mad_small<M>(x, acc);
+    } else {
+        u64 r;
+        asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(r) : "v"(x), "i"(M), "s"(acc) : "vcc");
+        return r;
+    }
+}
+
 // Terms are accumulated for words 1..11 first and word 0 last: in a partial
 // round only word 0 went through the S-box, so the other eleven products can
 // issue while its S-box chain is still running.
@@ -88,19 +103,38 @@ __device__ __forceinline__ void mds_term(const u64 s[WIDTH], u64 &a_lo, u64 &a_h
     if constexpr (K + 1 < WIDTH) mds_term<I, K + 1>(s, a_lo, a_hi);
 }
 
-template <int I>
-__device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], int r1) {
-    u64 a_lo = RC_SPLIT[r1][I][0];
-    u64 a_hi = RC_SPLIT[r1][I][1];
-    mds_term<I, 0>(s, a_lo, a_hi);
+template <int I, int END>
+__device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], const u64 (*rc)[2]) {
+    constexpr int J = 1;  // the first word of mds_term's order
+    u64 a_lo = mad_small_sacc<GOLDI_MDS[I][J]>(lo32(s[J]), rc[I][0]);
+    u64 a_hi = mad_small_sacc<GOLDI_MDS[I][J]>(hi32(s[J]), rc[I][1]);
+    mds_term<I, 1>(s, a_lo, a_hi);
     out[I] = reduce_split(a_lo, a_hi);
-    if constexpr (I + 1 < WIDTH) mds_rows<I + 1>(s, out, r1);
+    if constexpr (I + 1 < END) mds_rows<I + 1, END>(s, out, rc);
 }
 
-// s <- M s + C[r1]  (C[ROUNDS] = 0).
+#ifndef GOLDI_RC_GROUP
+#define GOLDI_RC_GROUP 6  // rows per batch of round-constant loads
+#endif
+
+template <int I0>
+__device__ __forceinline__ void mds_row_group(const u64 s[WIDTH], u64 out[WIDTH], int r1) {
+    constexpr int I1 = I0 + GOLDI_RC_GROUP < WIDTH ? I0 + GOLDI_RC_GROUP : WIDTH;
+    u64 rc[WIDTH][2];
+#pragma unroll
+    for (int i = I0; i < I1; i++) {
+        rc[i][0] = RC_SPLIT[r1][i][0];
+        rc[i][1] = RC_SPLIT[r1][i][1];
+    }
+    mds_rows<I0, I1>(s, out, rc);
+    if constexpr (I1 < WIDTH) mds_row_group<I1>(s, out, r1);
+}
+
+// s <- M s + C[r1]  (C[ROUNDS] = 0).  The constants of a group of rows are
+// read together (wave-uniform scalar loads), so one wait covers the group.
 __device__ __forceinline__ void mds_add_rc(u64 s[WIDTH], int r1) {
     u64 out[WIDTH];
-    mds_rows<0>(s, out, r1);
+    mds_row_group<0>(s, out, r1);
 #pragma unroll
     for (int i = 0; i < WIDTH; i++) s[i] = out[i];
 }
