@@ -34,7 +34,12 @@
  * Errors: every call returns a status code.  Inputs >= p are detected on the
  * device and give GOLDI_ENONCANON (output contents are then unspecified).
  * Null pointers, zero sizes or sizes whose byte counts overflow give
- * GOLDI_EINVAL before anything is launched.  HIP failures give GOLDI_EDEVICE;
+ * GOLDI_EINVAL before anything is launched; so do more than 2^32 - 256
+ * states or rows, since one kernel dispatch covers at most 2^32 - 1
+ * work-items.  A launch that would exceed that limit because the schedule
+ * knobs (goldi_tune_set) put many lanes on each item is refused with
+ * GOLDI_EINVAL when it is reached; kernels already enqueued by the same
+ * call then leave the output incomplete.  HIP failures give GOLDI_EDEVICE;
  * goldi_last_error() returns a thread-local message for the last failure.
  * No C++ exception crosses this interface.
  *

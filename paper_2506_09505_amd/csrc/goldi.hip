@@ -134,15 +134,26 @@ int timed_launch(const char *name, hipStream_t st, F launch) {
     return GOLDI_OK;
 }
 
-unsigned grid_for(size_t n) { return (unsigned)((n + goldi::BLOCK - 1) / goldi::BLOCK); }
+// One dispatch covers at most 2^32 - 1 work-items (the dispatch packet's
+// grid size is 32-bit), so a launch beyond that is refused, never truncated.
+constexpr size_t kMaxThreads = 0xFFFFFFFFull - (goldi::BLOCK - 1);
 
-constexpr size_t kMaxGrid = (size_t)0x7FFFFFFF * goldi::BLOCK / 16;  // up to 16 lanes per item
+int blocks_for(size_t items, size_t lanes, unsigned *blocks) {
+    size_t threads;
+    if (mul_overflows(items, lanes, &threads) || threads > kMaxThreads)
+        return fail(GOLDI_EINVAL, "a launch of %zu items x %zu lanes exceeds one dispatch (2^32 - 1 work-items)",
+                    items, lanes);
+    *blocks = (unsigned)((threads + goldi::BLOCK - 1) / goldi::BLOCK);
+    return GOLDI_OK;
+}
 
 // ---------------------------------------------------------------- launches
 
 int launch_permute(uint64_t *states, size_t n, uint32_t *status, hipStream_t st) {
+    unsigned g;
+    if (int rc = blocks_for(n, 1, &g)) return rc;
     return timed_launch("permute", st, [&] {
-        hipLaunchKernelGGL(goldi::k_permute, dim3(grid_for(n)), dim3(goldi::BLOCK), 0, st, states, n, status);
+        hipLaunchKernelGGL(goldi::k_permute, dim3(g), dim3(goldi::BLOCK), 0, st, states, n, status);
     });
 }
 
@@ -173,41 +184,46 @@ size_t quad_max_parents() { return g_quad_max_parents.load(std::memory_order_rel
 
 int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests, uint32_t *status,
                      hipStream_t st) {
+    unsigned g;
     if (n_rows <= l12_max_rows()) {
+        if (int rc = blocks_for(n_rows, 16, &g)) return rc;
         return timed_launch("leaf_hash_lane12", st, [&] {
-            hipLaunchKernelGGL(goldi::k_leaf_hash_lane12, dim3(grid_for(16 * n_rows)), dim3(goldi::BLOCK), 0, st,
-                               leaves, n_rows, n_cols, digests, status);
+            hipLaunchKernelGGL(goldi::k_leaf_hash_lane12, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
+                               digests, status);
         });
     }
     if (n_rows <= quad_max_rows()) {
+        if (int rc = blocks_for(n_rows, 4, &g)) return rc;
         return timed_launch("leaf_hash_quad", st, [&] {
-            hipLaunchKernelGGL(goldi::k_leaf_hash_quad, dim3(grid_for(4 * n_rows)), dim3(goldi::BLOCK), 0, st,
-                               leaves, n_rows, n_cols, digests, status);
+            hipLaunchKernelGGL(goldi::k_leaf_hash_quad, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
+                               digests, status);
         });
     }
+    if (int rc = blocks_for(n_rows, 1, &g)) return rc;
     return timed_launch("leaf_hash", st, [&] {
-        hipLaunchKernelGGL(goldi::k_leaf_hash, dim3(grid_for(n_rows)), dim3(goldi::BLOCK), 0, st, leaves, n_rows,
-                           n_cols, digests, status);
+        hipLaunchKernelGGL(goldi::k_leaf_hash, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols, digests,
+                           status);
     });
 }
 
 int launch_level(const uint64_t *child, size_t n_child, uint64_t *parent, hipStream_t st) {
     const size_t n_par = (n_child + 1) / 2;
+    unsigned g;
     if (n_par <= l12_max_parents()) {
+        if (int rc = blocks_for(n_par, 16, &g)) return rc;
         return timed_launch("level_lane12", st, [&] {
-            hipLaunchKernelGGL(goldi::k_level_lane12, dim3(grid_for(16 * n_par)), dim3(goldi::BLOCK), 0, st, child,
-                               n_child, parent);
+            hipLaunchKernelGGL(goldi::k_level_lane12, dim3(g), dim3(goldi::BLOCK), 0, st, child, n_child, parent);
         });
     }
     if (n_par <= quad_max_parents()) {
+        if (int rc = blocks_for(n_par, 4, &g)) return rc;
         return timed_launch("level_quad", st, [&] {
-            hipLaunchKernelGGL(goldi::k_level_quad, dim3(grid_for(4 * n_par)), dim3(goldi::BLOCK), 0, st, child,
-                               n_child, parent);
+            hipLaunchKernelGGL(goldi::k_level_quad, dim3(g), dim3(goldi::BLOCK), 0, st, child, n_child, parent);
         });
     }
+    if (int rc = blocks_for(n_par, 1, &g)) return rc;
     return timed_launch("level", st, [&] {
-        hipLaunchKernelGGL(goldi::k_level, dim3(grid_for(n_par)), dim3(goldi::BLOCK), 0, st, child, n_child,
-                           parent);
+        hipLaunchKernelGGL(goldi::k_level, dim3(g), dim3(goldi::BLOCK), 0, st, child, n_child, parent);
     });
 }
 
@@ -230,19 +246,23 @@ int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *
 size_t chunks_of(size_t n_cols) { return (n_cols + goldi::RATE - 1) / goldi::RATE; }
 
 // Launches one step of a batch: fills block_begin from per-tree item counts
-// (lanes_per_item = 1 or 4) and launches `kernel`.
+// (lanes_per_item = 1, 4 or 16) and launches `kernel`.
 template <class K, class... Extra>
 int launch_batch(const char *name, K kernel, goldi::Batch &b, const size_t *items, int lanes_per_item,
                  hipStream_t st, Extra... extra) {
-    uint32_t blocks = 0;
+    size_t blocks = 0;
     for (uint32_t t = 0; t < b.n_trees; t++) {
-        b.block_begin[t] = blocks;
-        blocks += (uint32_t)((items[t] * lanes_per_item + goldi::BLOCK - 1) / goldi::BLOCK);
+        unsigned g;
+        if (int rc = blocks_for(items[t], lanes_per_item, &g)) return rc;
+        b.block_begin[t] = (uint32_t)blocks;
+        blocks += g;
+        if (blocks * goldi::BLOCK > kMaxThreads)
+            return fail(GOLDI_EINVAL, "batched launch '%s' exceeds one dispatch (2^32 - 1 work-items)", name);
     }
-    b.block_begin[b.n_trees] = blocks;
+    b.block_begin[b.n_trees] = (uint32_t)blocks;
     if (blocks == 0) return GOLDI_OK;
     return timed_launch(name, st, [&] {
-        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(goldi::BLOCK), 0, st, b, extra...);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(goldi::BLOCK), 0, st, b, extra...);
     });
 }
 
@@ -402,7 +422,7 @@ int enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hi
 int validate_permute(const uint64_t *states, size_t n) {
     if (n == 0) return fail(GOLDI_EINVAL, "n must be >= 1");
     size_t bytes;
-    if (mul_overflows(n, goldi::WIDTH * sizeof(u64), &bytes) || n > kMaxGrid)
+    if (mul_overflows(n, goldi::WIDTH * sizeof(u64), &bytes) || n > kMaxThreads)
         return fail(GOLDI_EINVAL, "n = %zu is too large", n);
     return check_device_range(states, bytes, "states");
 }
@@ -412,7 +432,7 @@ int validate_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, const ui
     if (n_rows == 0 || n_cols == 0) return fail(GOLDI_EINVAL, "n_rows and n_cols must be >= 1");
     size_t cells, in_bytes, out_bytes;
     if (mul_overflows(n_rows, n_cols, &cells) || mul_overflows(cells, sizeof(u64), &in_bytes) ||
-        mul_overflows(out_nodes, goldi::DIGEST * sizeof(u64), &out_bytes) || n_rows > kMaxGrid)
+        mul_overflows(out_nodes, goldi::DIGEST * sizeof(u64), &out_bytes) || n_rows > kMaxThreads)
         return fail(GOLDI_EINVAL, "shape %zu x %zu is too large", n_rows, n_cols);
     int rc = check_device_range(leaves, in_bytes, "leaves");
     if (rc) return rc;

@@ -92,3 +92,26 @@ def test_error_text():
     assert L.goldi_strerror(goldi.GOLDI_ENONCANON) == b"input word not canonical (>= p)"
     assert isinstance(L.goldi_last_error(), bytes)
     assert ctypes.sizeof(goldi._Tree) == 32
+
+
+def test_dispatch_limit():
+    # One dispatch covers at most 2^32 - 1 work-items.  Too many states is
+    # refused before any buffer is inspected; a tree whose row count times the
+    # lanes per row (forced to 16 by the one-word-per-lane knob) crosses the
+    # limit is refused at its first launch, so nothing runs.
+    import torch
+    L = goldi.lib()
+    d = to_dev(uniform_states(4, seed=8))
+    assert L.goldi_poseidon_permute(d.data_ptr(), 1 << 32) == goldi.GOLDI_EINVAL
+    n = (1 << 28) + 16
+    lv = torch.empty(n, dtype=torch.uint64, device="cuda:0")
+    out = torch.empty(goldi.goldi_merkle_num_nodes(n) * 4, dtype=torch.uint64, device="cuda:0")
+    old = goldi.goldi_tune_get("lane12_max_rows")
+    try:
+        goldi.goldi_tune_set("lane12_max_rows", 1 << 40)
+        assert L.goldi_merkle_build(lv.data_ptr(), n, 1, out.data_ptr()) == goldi.GOLDI_EINVAL
+        assert b"dispatch" in L.goldi_last_error()
+    finally:
+        goldi.goldi_tune_set("lane12_max_rows", old)
+    del lv, out
+    torch.cuda.empty_cache()
