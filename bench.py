@@ -61,10 +61,16 @@ def perms_per_build(n_rows: int, n_cols: int) -> int:
     return n_rows * ((n_cols + 7) // 8) + (n_rows - 1)
 
 
+# The device code of the build kernels (their bodies, block size and
+# constants); host-side files do not change what a kernel reads or writes.
+DEVICE_SOURCES = ("field.hpp", "poseidon.hpp", "poseidon_quad.hpp", "poseidon_lane12.hpp", "kernels.hpp",
+                  "poseidon12_constants.inc")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2506_09505_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in DEVICE_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
