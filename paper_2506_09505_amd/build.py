@@ -28,34 +28,37 @@ def sources():
     return [os.path.join(CSRC, "goldi.hip"), os.path.join(CSRC, "server.hip")]
 
 
-def build(verbose: bool = False) -> str:
-    from . import gen_constants
-    gen_constants.main()
-    os.makedirs(os.path.join(HERE, "_special"), exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + sources() + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+def _jobs(gen_constants):
+    """(output, sources, extra flags) of every library; the test-only ones go
+    to _special/."""
+    yield LIB, sources(), []
     # The Table-1 function library (device field operations, rates).
-    tmp = FB_LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                                 os.path.join(CSRC, "fieldbench.hip"), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, FB_LIB)
+    yield FB_LIB, [os.path.join(CSRC, "fieldbench.hip")], []
     # Test-only libraries compiled against special instances with closed forms.
     for inc in gen_constants.write_specials():
         name = os.path.basename(inc)[len("special_"):-len(".inc")]
-        out = special_lib(name)
+        yield special_lib(name), sources(), ['-DGOLDI_CONSTANTS_INC="%s"' % os.path.basename(inc)]
+    # Test-only: the seeded instance with dense partial rounds everywhere, so
+    # that form stays checked against the oracle.
+    yield special_lib("dense"), sources(), ["-DGOLDI_PARTIAL_SPARSE=0"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every library (hipcc runs in parallel, one process each)."""
+    from . import gen_constants
+    gen_constants.main()
+    os.makedirs(os.path.join(HERE, "_special"), exist_ok=True)
+    running = []
+    for out, srcs, extra in _jobs(gen_constants):
         tmp = out + ".tmp%d" % os.getpid()
-        cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                                     '-DGOLDI_CONSTANTS_INC="%s"' % os.path.basename(inc)] + sources() + ["-o", tmp]
+        cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + extra + srcs + ["-o", tmp]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        running.append((out, tmp, cmd, subprocess.Popen(cmd)))
+    failed = [cmd for out, tmp, cmd, proc in running if proc.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    for out, tmp, cmd, proc in running:
         os.replace(tmp, out)
     return LIB
 

@@ -14,11 +14,12 @@
 // and one partial-round body keep the code small enough for the instruction
 // cache, which a fully unrolled permutation (~17k instructions) would not.
 //
-// Partial rounds use the dense matrix too.  Alg. 1 instead multiplies by a
-// sparse matrix (MDSPartial) with full-size 64-bit entries.  On gfx950 the
-// 32x32 multiply-add issues at the full VALU rate, and a dense product with
-// 6-bit entries costs 2 multiply-adds per term, so the dense form costs about
-// as much as the sparse one while needing no derived constants.
+// Partial rounds: by default in the sparse form of Alg. 1 (MDSPartial: one
+// pre-matrix, then per round a matrix that is the identity apart from a full
+// first row and first column, with full-size 64-bit entries), which measured
+// faster on MI355X than the dense product with 6-bit entries (2 multiply-adds
+// per term).  GOLDI_PARTIAL_SPARSE=0 selects the dense form, as does an
+// instance whose lower-right 11 x 11 block of M is singular (no sparse form).
 #pragma once
 #include "field.hpp"
 #ifdef GOLDI_CONSTANTS_INC
@@ -47,7 +48,7 @@ __device__ __forceinline__ u64 sbox(u64 x) {
     return mul(x4, x3);
 }
 
-// V = a_lo + a_hi 2^32 with a_lo, a_hi < 2^43, reduced to a weak word:
+// V = a_lo + a_hi 2^32 with any a_lo and a_hi < 2^64 - 2^32, reduced to a weak word:
 // V = w2 2^64 + (w1 2^32 + lo32(a_lo)) with w1 = hi32(a_lo) + lo32(a_hi)
 // and w2 = hi32(a_hi) + carry, then 2^64 = 2^32 - 1.
 __device__ __forceinline__ u64 reduce_split(u64 a_lo, u64 a_hi) {
@@ -145,6 +146,124 @@ __device__ __forceinline__ void full_round(u64 s[WIDTH], int r) {
     mds_add_rc(s, r + 1);
 }
 
+// ---------------------------------------------------------------------------
+// Partial rounds in sparse form (Sec. 2.4, Alg. 1): the 11 x 11 block of M
+// is conjugated away, so that after one pre-matrix each partial round
+// multiplies by a matrix whose first row and first column are full and whose
+// rest is the identity, and only word 0 receives a round constant.  The
+// constants are derived from C and M by the generator (sparse_form).
+//   new x0 = m00 s + sum_i row[i] x_i + k     (s = the S-box output)
+//   x_i   += col[i] s                         (i = 1..11)
+// Full-width entries of a dot product come as three 22-bit limbs, so each
+// 32 x 22-bit product is below 2^54 and the dozen terms of a dot product add
+// up in six 64-bit accumulators without carries; they are combined once.
+#ifndef GOLDI_PARTIAL_SPARSE
+#define GOLDI_PARTIAL_SPARSE 1
+#endif
+#if GOLDI_PARTIAL_SPARSE && GOLDI_SPARSE_OK
+#define GOLDI_USE_SPARSE 1
+__constant__ u32 SP_K[PARTIAL + 1][3] = GOLDI_SP_K_INIT;
+__constant__ u32 SP_CEND[WIDTH - 1][2] = GOLDI_SP_CEND_INIT;
+__constant__ u32 SP_ROW[PARTIAL][WIDTH - 1][3] = GOLDI_SP_ROW_INIT;
+__constant__ u32 SP_COL[PARTIAL][WIDTH - 1][2] = GOLDI_SP_COL_INIT;
+__constant__ u32 SP_PRE_M[WIDTH - 1][WIDTH][3] = GOLDI_SP_PRE_M_INIT;
+#else
+#define GOLDI_USE_SPARSE 0
+#endif
+
+#if GOLDI_USE_SPARSE
+// sum_i x_i c_i with c_i = c_i0 + c_i1 2^22 + c_i2 2^44: a0[j] = sum of
+// lo32(x_i) c_ij, a1[j] = sum of hi32(x_i) c_ij.
+struct Dot6 {
+    u64 a0[3], a1[3];
+};
+
+__device__ __forceinline__ void dot_init(Dot6 &d, const u32 (&k)[3]) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        d.a0[j] = k[j];
+        d.a1[j] = 0;
+    }
+}
+
+__device__ __forceinline__ void dot_term(Dot6 &d, u64 x, const u32 (&c)[3]) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        d.a0[j] = mad32(lo32(x), c[j], d.a0[j]);
+        d.a1[j] = mad32(hi32(x), c[j], d.a1[j]);
+    }
+}
+
+// (r 2^22 + x) mod p as a weak word, for any words r and x.
+__device__ __forceinline__ u64 shl22_add(u64 r, u64 x) {
+    u64 lo;
+    const bool c = __builtin_add_overflow(r << 22, x, &lo);
+    return mad_eps_fold((hi32(r) >> 10) + (u32)c, lo);
+}
+
+__device__ __forceinline__ u64 dot_finish(const Dot6 &d) {
+    const u64 r0 = reduce_split(d.a0[0], d.a1[0]);
+    const u64 r1 = reduce_split(d.a0[1], d.a1[1]);
+    const u64 r2 = reduce_split(d.a0[2], d.a1[2]);
+    return shl22_add(shl22_add(r2, r1), r0);
+}
+
+// c s + z (mod p) for a constant c = c1 2^32 + c0 held in scalar registers,
+// as a weak word: the 128-bit c s + z (z enters as the addend of the lowest
+// partial product; the carries stay below 2^64, see the bounds below), then
+// reduced.  t = s1 c0 + ((s0 c0 + z) >> 32) <= (2^32-1)^2 + 2^33 - 3 < 2^64.
+__device__ __forceinline__ u64 mul_add(u64 s, u32 c0, u32 c1, u64 z) {
+    const u32 s0 = lo32(s), s1 = hi32(s);
+    u64 p00, k1, u, k2;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(p00), "=s"(k1) : "v"(s0), "s"(c0), "v"(z));
+    u32 kw, cw;
+    asm("s_nop 1\n\tv_addc_co_u32 %0, vcc, 0, 0, %1" : "=v"(kw) : "s"(k1) : "vcc");
+    const u64 t = mad32(s1, c0, mk64(hi32(p00), kw));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(u), "=s"(k2) : "v"(s0), "s"(c1), "v"(t));
+    asm("s_nop 1\n\tv_addc_co_u32 %0, vcc, 0, 0, %1" : "=v"(cw) : "s"(k2) : "vcc");
+    return reduce128(mk64(lo32(p00), lo32(u)), mad32(s1, c1, mk64(hi32(u), cw)));
+}
+
+// The last opening full round's matrix with the pre-matrix folded in:
+// row 0 is M's (plus the scalar k_4), rows 1..11 are diag(1, Mh^22) M.
+__device__ __forceinline__ void pre_matrix(u64 s[WIDTH]) {
+    u64 out[WIDTH];
+    const u64 k4[1][2] = {GOLDI_SP_K4_SPLIT};
+    mds_rows<0, 1>(s, out, k4);
+    // Rows 1..11 one per iteration of a rolled loop (the scalar registers
+    // hold one row's 36 constant limbs at a time); each new row enters a
+    // shift register, so after the last iteration out[i] holds row i.
+#pragma nounroll
+    for (int i = 1; i < WIDTH; i++) {
+        Dot6 d;
+        const u32 zero[3] = {0, 0, 0};
+        dot_init(d, zero);
+#pragma unroll
+        for (int j = 0; j < WIDTH; j++) dot_term(d, s[j], SP_PRE_M[i - 1][j]);
+#pragma unroll
+        for (int k = 1; k < WIDTH - 1; k++) out[k] = out[k + 1];
+        out[WIDTH - 1] = dot_finish(d);
+    }
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = out[i];
+}
+
+// Partial round HALF_FULL + j; the constant that follows is k of the next
+// partial round, or for the last one the closing constant's word 0.
+__device__ __forceinline__ void sparse_round(u64 s[WIDTH], int j) {
+    const u64 x0 = sbox(s[0]);
+    Dot6 d;
+    dot_init(d, SP_K[j + 1]);
+    d.a0[0] = mad_small<GOLDI_MDS[0][0]>(lo32(x0), d.a0[0]);
+    d.a1[0] = mad_small<GOLDI_MDS[0][0]>(hi32(x0), d.a1[0]);
+#pragma unroll
+    for (int i = 1; i < WIDTH; i++) dot_term(d, s[i], SP_ROW[j][i - 1]);
+#pragma unroll
+    for (int i = 1; i < WIDTH; i++) s[i] = mul_add(x0, SP_COL[j][i - 1][0], SP_COL[j][i - 1][1], s[i]);
+    s[0] = dot_finish(d);
+}
+#endif
+
 __device__ __forceinline__ void partial_round(u64 s[WIDTH], int r) {
     s[0] = sbox(s[0]);
     mds_add_rc(s, r + 1);
@@ -154,13 +273,29 @@ __device__ __forceinline__ void partial_round(u64 s[WIDTH], int r) {
 __device__ __forceinline__ void permute(u64 s[WIDTH]) {
 #pragma unroll
     for (int i = 0; i < WIDTH; i++) s[i] = add_weak(s[i], mk64(lo32(RC_SPLIT[0][i][0]), lo32(RC_SPLIT[0][i][1])));
-#pragma nounroll
-    for (int r = 0; r < HALF_FULL; r++) full_round(s, r);
 #ifndef GOLDI_PARTIAL_UNROLL
 #define GOLDI_PARTIAL_UNROLL 2
 #endif
+#if GOLDI_USE_SPARSE
+#pragma nounroll
+    for (int r = 0; r < HALF_FULL; r++) {
+#pragma unroll
+        for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
+        if (r + 1 < HALF_FULL)
+            mds_add_rc(s, r + 1);
+        else
+            pre_matrix(s);
+    }
+#pragma unroll GOLDI_PARTIAL_UNROLL
+    for (int j = 0; j < PARTIAL; j++) sparse_round(s, j);
+#pragma unroll
+    for (int i = 1; i < WIDTH; i++) s[i] = add_weak(s[i], mk64(SP_CEND[i - 1][0], SP_CEND[i - 1][1]));
+#else
+#pragma nounroll
+    for (int r = 0; r < HALF_FULL; r++) full_round(s, r);
 #pragma unroll GOLDI_PARTIAL_UNROLL
     for (int r = HALF_FULL; r < HALF_FULL + PARTIAL; r++) partial_round(s, r);
+#endif
 #pragma nounroll
     for (int r = HALF_FULL + PARTIAL; r < ROUNDS; r++) full_round(s, r);
 }

@@ -11,8 +11,15 @@ tables the kernels compile against:
   constants enter at the start of each round, Sec. 2.4).
 * ``GOLDI_MDS[12][12]``: the small matrix entries (they fit 8 bits, as the
   paper's ``mult_72`` / ``mmult_4x12_8`` functions assume, Table 1).
+* the constants of the sparse form of the partial rounds (Sec. 2.4, Alg. 1:
+  a dense pre-matrix once, then per partial round a sparse matrix whose first
+  row and first column are full and whose remainder is the identity), derived
+  from C and M by ``sparse_form`` below.  Full-width entries that enter dot
+  products are split into three 22-bit limbs (a 32 x 22-bit product is below
+  2^54, so a dozen of them add up in 64 bits without carries); entries that
+  multiply one word are split into 32-bit halves.
 
-The script only reformats; it does no field arithmetic.
+Apart from ``sparse_form`` the script only reformats.
 """
 
 from __future__ import annotations
@@ -20,10 +27,130 @@ from __future__ import annotations
 import json
 import os
 
+P = (1 << 64) - (1 << 32) + 1
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SPEC = os.path.join(ROOT, "synth", "poseidon12.json")
 OUT = os.path.join(HERE, "csrc", "poseidon12_constants.inc")
+
+
+def _mm(a, b):
+    return [[sum(a[i][k] * b[k][j] for k in range(len(b))) % P for j in range(len(b[0]))] for i in range(len(a))]
+
+
+def _mv(a, x):
+    return [sum(a[i][k] * x[k] for k in range(len(x))) % P for i in range(len(a))]
+
+
+def _identity(n):
+    return [[int(i == j) for j in range(n)] for i in range(n)]
+
+
+def _inverse(m):
+    """Inverse of a square matrix mod p (Gauss-Jordan), or None if singular."""
+    n = len(m)
+    a = [[m[i][j] % P for j in range(n)] + _identity(n)[i] for i in range(n)]
+    for c in range(n):
+        piv = next((r for r in range(c, n) if a[r][c]), None)
+        if piv is None:
+            return None
+        a[c], a[piv] = a[piv], a[c]
+        inv = pow(a[c][c], P - 2, P)
+        a[c] = [v * inv % P for v in a[c]]
+        for r in range(n):
+            if r != c and a[r][c]:
+                f = a[r][c]
+                a[r] = [(x - f * y) % P for x, y in zip(a[r], a[c])]
+    return [row[n:] for row in a]
+
+
+def _power(m, e):
+    r = _identity(len(m))
+    for _ in range(e):
+        r = _mm(r, m)
+    return r
+
+
+def sparse_form(rc, mds, half_full: int = 4, partial: int = 22):
+    """Constants of the partial rounds in sparse form (Sec. 2.4, Alg. 1).
+
+    Write M = [[m00, w^T], [v, Mh]] with Mh the lower-right 11 x 11 block.
+    With D_j = diag(1, Mh^(j - partial)) (j = 0..partial), the matrices
+    D_j^-1 M D_(j-1) have the identity as lower-right block, first row
+    (m00, w^T Mh^(j - 1 - partial)) and first column Mh^(partial - j) v; the
+    state entering the partial rounds is multiplied once by
+    D_0^-1 = diag(1, Mh^partial) and D_partial = I leaves nothing behind.
+    Only word 0 passes the S-box in a partial round, so a round constant's
+    words 1..11 can be moved through the matrix into the next round's
+    constant; what is left before each S-box is a scalar k_r on word 0, and
+    the carry after the last partial round joins the first constant of the
+    closing full rounds.
+
+    Returns None when Mh is singular (no sparse form exists), else a dict:
+      k[j]   = k_(half_full + j), j = 0..partial-1 (scalar constants);
+      c_end  = the 12-word constant added after the last partial round;
+      row[j] = first-row entries 1..11 of partial round half_full + j;
+      col[j] = first-column entries 1..11 of that round;
+      pre    = Mh^partial (11 x 11);
+      pre_m  = rows 1..11 of diag(1, Mh^partial) M (11 x 12): the pre-matrix
+               folded into the matrix of the last opening full round."""
+    w12 = len(mds)
+    mh = [row[1:] for row in mds[1:]]
+    mh_inv = _inverse(mh)
+    if mh_inv is None:
+        return None
+    w = mds[0][1:]
+    v = [mds[i][0] for i in range(1, w12)]
+    row, col = [], []
+    for j in range(1, partial + 1):
+        back = _power(mh_inv, partial + 1 - j)          # Mh^(j - 1 - partial)
+        row.append([sum(w[k] * back[k][i] for k in range(w12 - 1)) % P for i in range(w12 - 1)])
+        col.append(_mv(_power(mh, partial - j), v))
+    pre = _power(mh, partial)
+    pre_m = _mm(pre, [r[:] for r in mds[1:]])
+    carry = [0] * w12
+    k = []
+    for r in range(half_full, half_full + partial):
+        d = [(rc[r][i] + carry[i]) % P for i in range(w12)]
+        k.append(d[0])
+        carry = _mv(mds, [0] + d[1:])
+    c_end = [(rc[half_full + partial][i] + carry[i]) % P for i in range(w12)]
+    return {"k": k, "c_end": c_end, "row": row, "col": col, "pre": pre, "pre_m": pre_m}
+
+
+def _limbs22(x: int):
+    return [x & 0x3FFFFF, (x >> 22) & 0x3FFFFF, x >> 44]
+
+
+def _c_array(name: str, ctype: str, dims, flat) -> str:
+    body = ", ".join("0x%xu" % v for v in flat)
+    return "#define %s_INIT {%s}  /* %s%s */" % (name, body, ctype, "".join("[%d]" % d for d in dims))
+
+
+def render_sparse(rc, mds) -> list:
+    sp = sparse_form(rc, mds)
+    lines = ["// Partial rounds in sparse form (see gen_constants.sparse_form)."]
+    if sp is None:
+        lines.append("#define GOLDI_SPARSE_OK 0  // the lower-right 11 x 11 block of M is singular")
+        sp = {"k": [0] * 22, "c_end": [0] * 12, "row": [[0] * 11] * 22, "col": [[0] * 11] * 22,
+              "pre_m": [[0] * 12] * 11}
+    else:
+        lines.append("#define GOLDI_SPARSE_OK 1")
+    k = sp["k"] + [sp["c_end"][0]]
+    lines.append("// GOLDI_SP_K[j]: 22-bit limbs of k_(4+j); j = 22: word 0 of the closing constant.")
+    lines.append(_c_array("GOLDI_SP_K", "u32", [23, 3], [l for x in k for l in _limbs22(x)]))
+    lines.append("// GOLDI_SP_CEND[i]: 32-bit halves of word i+1 of the closing constant.")
+    lines.append(_c_array("GOLDI_SP_CEND", "u32", [11, 2], [h for x in sp["c_end"][1:] for h in (x & 0xFFFFFFFF, x >> 32)]))
+    lines.append("// GOLDI_SP_ROW[j][i]: 22-bit limbs of first-row entry i+1 of partial round 4+j.")
+    lines.append(_c_array("GOLDI_SP_ROW", "u32", [22, 11, 3], [l for r in sp["row"] for x in r for l in _limbs22(x)]))
+    lines.append("// GOLDI_SP_COL[j][i]: 32-bit halves of first-column entry i+1 of partial round 4+j.")
+    lines.append(_c_array("GOLDI_SP_COL", "u32", [22, 11, 2], [h for r in sp["col"] for x in r for h in (x & 0xFFFFFFFF, x >> 32)]))
+    lines.append("// GOLDI_SP_PRE_M[i][j]: 22-bit limbs of row i+1, column j of diag(1, Mh^22) M.")
+    lines.append(_c_array("GOLDI_SP_PRE_M", "u32", [11, 12, 3], [l for r in sp["pre_m"] for x in r for l in _limbs22(x)]))
+    k4 = sp["k"][0]
+    lines.append("// GOLDI_SP_K4_SPLIT: k_4 as the {lo32, 0}, {hi32, 0} pair of a matrix row's addends.")
+    lines.append("#define GOLDI_SP_K4_SPLIT {0x%08xull, 0x%08xull}" % (k4 & 0xFFFFFFFF, k4 >> 32))
+    return lines
 
 
 def render(spec: dict, source: str = "synth/poseidon12.json") -> str:
@@ -47,6 +174,7 @@ def render(spec: dict, source: str = "synth/poseidon12.json") -> str:
         cells = ", ".join("{0x%08xull, 0x%08xull}" % (v & 0xFFFFFFFF, v >> 32) for v in row)
         lines.append("    {%s}, \\" % cells)
     lines.append("}")
+    lines.extend(render_sparse([[int(v) for v in row] for row in spec["rc"]], [[int(v) for v in row] for row in mds]))
     return "\n".join(lines) + "\n"
 
 

@@ -3,6 +3,11 @@
 import numpy as np
 
 
+def banner(msg):
+    """Names the case before its GPU work starts."""
+    print("[case] " + msg, flush=True)
+
+
 def torch_mod():
     import torch
     return torch

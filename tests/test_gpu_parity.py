@@ -9,7 +9,7 @@ import oracle
 import paper_2506_09505_amd as goldi
 from synth.inputs import GOLDILOCKS_P, edge_states, leaves_colmajor, uniform_states
 
-from .gpu_util import level_offsets, rows_from_colmajor, to_dev, to_host
+from .gpu_util import banner, level_offsets, rows_from_colmajor, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 P = GOLDILOCKS_P
@@ -18,10 +18,6 @@ P = GOLDILOCKS_P
 @pytest.fixture(scope="module")
 def prm():
     return oracle.spec_params()
-
-
-def banner(msg):
-    print("[case] " + msg, flush=True)
 
 
 def test_library_is_native():

@@ -1,0 +1,89 @@
+"""The partial rounds in sparse form (Sec. 2.4, Alg. 1: a pre-matrix once,
+then per round a matrix whose first row and column are full and whose rest is
+the identity, with scalar round constants) must be the textbook permutation.
+
+``gen_constants.sparse_form`` derives those constants from C and M; here they
+are evaluated in the sparse shape, in Python integers, and compared with the
+oracle's dense textbook permutation on random and edge states, for the seeded
+instance and for the special test instances.  A wrong power of the 11 x 11
+block, a transposed row or column, a misplaced scalar constant or a lost
+carry changes the permutation and fails."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_09505_amd import gen_constants as gc
+from synth.constants import load_constants
+from synth.inputs import EDGE_WORDS, uniform_states
+
+P = gc.P
+W = 12
+
+
+def sbox(x):
+    return pow(x, 7, P)
+
+
+def sparse_permute(x, rc, mds, sp):
+    """Sparse-form evaluation: rounds 0..2 dense; round 3 with the pre-matrix
+    folded into its matrix; 22 sparse partial rounds; rounds 26..29 dense."""
+    x = [(x[i] + rc[0][i]) % P for i in range(W)]
+    for r in range(3):
+        y = [sbox(t) for t in x]
+        x = [(sum(mds[i][j] * y[j] for j in range(W)) + rc[r + 1][i]) % P for i in range(W)]
+    y = [sbox(t) for t in x]
+    x = [(sum(mds[0][j] * y[j] for j in range(W)) + sp["k"][0]) % P]
+    x += [sum(sp["pre_m"][i][j] * y[j] for j in range(W)) % P for i in range(W - 1)]
+    for j in range(22):
+        s = sbox(x[0])
+        nxt = sp["k"][j + 1] if j < 21 else sp["c_end"][0]
+        x0 = (mds[0][0] * s + sum(sp["row"][j][i] * x[i + 1] for i in range(W - 1)) + nxt) % P
+        rest = [(x[i + 1] + sp["col"][j][i] * s) % P for i in range(W - 1)]
+        x = [x0] + rest
+    x = [x[0]] + [(x[i] + sp["c_end"][i]) % P for i in range(1, W)]
+    for r in range(26, 30):
+        y = [sbox(t) for t in x]
+        x = [(sum(mds[i][j] * y[j] for j in range(W)) + (rc[r + 1][i] if r < 29 else 0)) % P for i in range(W)]
+    return x
+
+
+def _states(n, seed):
+    s = uniform_states(n, seed=seed).astype(object).tolist()
+    edge = [int(e) for e in EDGE_WORDS]
+    s.append([edge[i % len(edge)] for i in range(W)])
+    s.append([edge[(3 * i + 1) % len(edge)] for i in range(W)])
+    return s
+
+
+def test_sparse_form_equals_textbook_seeded():
+    rc, mds = load_constants()
+    sp = gc.sparse_form(rc, mds)
+    assert sp is not None
+    states = _states(12, seed=40)
+    want = oracle.permute(oracle.Params(rc, mds), np.array(states, dtype=np.uint64))
+    for st, w in zip(states, want):
+        assert sparse_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
+
+
+@pytest.mark.parametrize("name", ["identity", "const"])
+def test_sparse_form_equals_textbook_special(name):
+    spec = gc.special_specs()[name]
+    rc = [[int(v) for v in row] for row in spec["rc"]]
+    mds = spec["mds"]
+    sp = gc.sparse_form(rc, mds)
+    states = _states(4, seed=41)
+    want = oracle.permute(oracle.Params(rc, mds), np.array(states, dtype=np.uint64))
+    for st, w in zip(states, want):
+        assert sparse_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
+
+
+def test_sparse_form_absent_when_block_singular():
+    spec = gc.special_specs()["shift"]
+    assert gc.sparse_form([[int(v) for v in row] for row in spec["rc"]], spec["mds"]) is None
+
+
+def test_limb_split_roundtrip():
+    for x in [0, 1, P - 1, 2**63, 0x123456789ABCDEF0 % P]:
+        l = gc._limbs22(x)
+        assert all(v < 2**22 for v in l) and l[0] + (l[1] << 22) + (l[2] << 44) == x
