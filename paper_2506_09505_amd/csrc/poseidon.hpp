@@ -154,9 +154,11 @@ __device__ __forceinline__ void full_round(u64 s[WIDTH], int r) {
 // constants are derived from C and M by the generator (sparse_form).
 //   new x0 = m00 s + sum_i row[i] x_i + k     (s = the S-box output)
 //   x_i   += col[i] s                         (i = 1..11)
-// Full-width entries of a dot product come as three 22-bit limbs, so each
-// 32 x 22-bit product is below 2^54 and the dozen terms of a dot product add
-// up in six 64-bit accumulators without carries; they are combined once.
+// Full-width entries come as three 22-bit limbs, so each 32 x 22-bit product
+// is below 2^54 and the dozen terms of a dot product add up in six 64-bit
+// accumulators without carries; they are combined once.  The column update
+// multiplies the limbs by s, s 2^22 and s 2^44 (mod p), computed once per
+// round.
 #ifndef GOLDI_PARTIAL_SPARSE
 #define GOLDI_PARTIAL_SPARSE 1
 #endif
@@ -165,7 +167,7 @@ __device__ __forceinline__ void full_round(u64 s[WIDTH], int r) {
 __constant__ u32 SP_K[PARTIAL + 1][3] = GOLDI_SP_K_INIT;
 __constant__ u32 SP_CEND[WIDTH - 1][2] = GOLDI_SP_CEND_INIT;
 __constant__ u32 SP_ROW[PARTIAL][WIDTH - 1][3] = GOLDI_SP_ROW_INIT;
-__constant__ u32 SP_COL[PARTIAL][WIDTH - 1][2] = GOLDI_SP_COL_INIT;
+__constant__ u32 SP_COL22[PARTIAL][WIDTH - 1][3] = GOLDI_SP_COL22_INIT;
 __constant__ u32 SP_PRE_M[WIDTH - 1][WIDTH][3] = GOLDI_SP_PRE_M_INIT;
 #else
 #define GOLDI_USE_SPARSE 0
@@ -208,20 +210,21 @@ __device__ __forceinline__ u64 dot_finish(const Dot6 &d) {
     return shl22_add(shl22_add(r2, r1), r0);
 }
 
-// c s + z (mod p) for a constant c = c1 2^32 + c0 held in scalar registers,
-// as a weak word: the 128-bit c s + z (z enters as the addend of the lowest
-// partial product; the carries stay below 2^64, see the bounds below), then
-// reduced.  t = s1 c0 + ((s0 c0 + z) >> 32) <= (2^32-1)^2 + 2^33 - 3 < 2^64.
-__device__ __forceinline__ u64 mul_add(u64 s, u32 c0, u32 c1, u64 z) {
-    const u32 s0 = lo32(s), s1 = hi32(s);
-    u64 p00, k1, u, k2;
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(p00), "=s"(k1) : "v"(s0), "s"(c0), "v"(z));
-    u32 kw, cw;
-    asm("s_nop 1\n\tv_addc_co_u32 %0, vcc, 0, 0, %1" : "=v"(kw) : "s"(k1) : "vcc");
-    const u64 t = mad32(s1, c0, mk64(hi32(p00), kw));
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(u), "=s"(k2) : "v"(s0), "s"(c1), "v"(t));
-    asm("s_nop 1\n\tv_addc_co_u32 %0, vcc, 0, 0, %1" : "=v"(cw) : "s"(k2) : "vcc");
-    return reduce128(mk64(lo32(p00), lo32(u)), mad32(s1, c1, mk64(hi32(u), cw)));
+// r 2^22 mod p as a weak word.
+__device__ __forceinline__ u64 shl22(u64 r) { return mad_eps_fold(hi32(r) >> 10, r << 22); }
+
+// z + c s (mod p) with c = g0 + g1 2^22 + g2 2^44 and sh = {s, s 2^22, s 2^44}
+// (mod p): six 32 x 22-bit products into a low and a high accumulator
+// (each below 3 2^54 + 2^32), then one split reduction.
+__device__ __forceinline__ u64 col_update(u64 z, const u64 (&sh)[3], const u32 (&g)[3]) {
+    u64 a_lo = mad32(lo32(sh[0]), g[0], (u64)lo32(z));
+    u64 a_hi = mad32(hi32(sh[0]), g[0], (u64)hi32(z));
+#pragma unroll
+    for (int j = 1; j < 3; j++) {
+        a_lo = mad32(lo32(sh[j]), g[j], a_lo);
+        a_hi = mad32(hi32(sh[j]), g[j], a_hi);
+    }
+    return reduce_split(a_lo, a_hi);
 }
 
 // The last opening full round's matrix with the pre-matrix folded in:
@@ -258,8 +261,10 @@ __device__ __forceinline__ void sparse_round(u64 s[WIDTH], int j) {
     d.a1[0] = mad_small<GOLDI_MDS[0][0]>(hi32(x0), d.a1[0]);
 #pragma unroll
     for (int i = 1; i < WIDTH; i++) dot_term(d, s[i], SP_ROW[j][i - 1]);
+    const u64 x1 = shl22(x0);
+    const u64 sh[3] = {x0, x1, shl22(x1)};
 #pragma unroll
-    for (int i = 1; i < WIDTH; i++) s[i] = mul_add(x0, SP_COL[j][i - 1][0], SP_COL[j][i - 1][1], s[i]);
+    for (int i = 1; i < WIDTH; i++) s[i] = col_update(s[i], sh, SP_COL22[j][i - 1]);
     s[0] = dot_finish(d);
 }
 #endif

@@ -16,8 +16,7 @@ tables the kernels compile against:
   row and first column are full and whose remainder is the identity), derived
   from C and M by ``sparse_form`` below.  Full-width entries that enter dot
   products are split into three 22-bit limbs (a 32 x 22-bit product is below
-  2^54, so a dozen of them add up in 64 bits without carries); entries that
-  multiply one word are split into 32-bit halves.
+  2^54, so a dozen of them add up in 64 bits without carries).
 
 Apart from ``sparse_form`` the script only reformats.
 """
@@ -143,8 +142,8 @@ def render_sparse(rc, mds) -> list:
     lines.append(_c_array("GOLDI_SP_CEND", "u32", [11, 2], [h for x in sp["c_end"][1:] for h in (x & 0xFFFFFFFF, x >> 32)]))
     lines.append("// GOLDI_SP_ROW[j][i]: 22-bit limbs of first-row entry i+1 of partial round 4+j.")
     lines.append(_c_array("GOLDI_SP_ROW", "u32", [22, 11, 3], [l for r in sp["row"] for x in r for l in _limbs22(x)]))
-    lines.append("// GOLDI_SP_COL[j][i]: 32-bit halves of first-column entry i+1 of partial round 4+j.")
-    lines.append(_c_array("GOLDI_SP_COL", "u32", [22, 11, 2], [h for r in sp["col"] for x in r for h in (x & 0xFFFFFFFF, x >> 32)]))
+    lines.append("// GOLDI_SP_COL22[j][i]: 22-bit limbs of first-column entry i+1 of partial round 4+j.")
+    lines.append(_c_array("GOLDI_SP_COL22", "u32", [22, 11, 3], [l for r in sp["col"] for x in r for l in _limbs22(x)]))
     lines.append("// GOLDI_SP_PRE_M[i][j]: 22-bit limbs of row i+1, column j of diag(1, Mh^22) M.")
     lines.append(_c_array("GOLDI_SP_PRE_M", "u32", [11, 12, 3], [l for r in sp["pre_m"] for x in r for l in _limbs22(x)]))
     k4 = sp["k"][0]
