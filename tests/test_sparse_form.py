@@ -48,6 +48,32 @@ def sparse_permute(x, rc, mds, sp):
     return x
 
 
+def paired_permute(x, rc, mds, sp):
+    """The same with partial rounds in pairs, as the kernels take them: the
+    second dot product uses the words from before the first column update
+    plus beta times the first S-box output; both column terms are added at
+    once."""
+    x = [(x[i] + rc[0][i]) % P for i in range(W)]
+    for r in range(3):
+        y = [sbox(t) for t in x]
+        x = [(sum(mds[i][j] * y[j] for j in range(W)) + rc[r + 1][i]) % P for i in range(W)]
+    y = [sbox(t) for t in x]
+    x = [(sum(mds[0][j] * y[j] for j in range(W)) + sp["k"][0]) % P]
+    x += [sum(sp["pre_m"][i][j] * y[j] for j in range(W)) % P for i in range(W - 1)]
+    for j in range(0, 22, 2):
+        a = sbox(x[0])
+        b = sbox((mds[0][0] * a + sum(sp["row"][j][i] * x[i + 1] for i in range(W - 1)) + sp["k"][j + 1]) % P)
+        nxt = sp["k"][j + 2] if j + 2 < 22 else sp["c_end"][0]
+        x0 = (mds[0][0] * b + sum(sp["row"][j + 1][i] * x[i + 1] for i in range(W - 1))
+              + sp["beta"][j // 2] * a + nxt) % P
+        x = [x0] + [(x[i + 1] + sp["col"][j][i] * a + sp["col"][j + 1][i] * b) % P for i in range(W - 1)]
+    x = [x[0]] + [(x[i] + sp["c_end"][i]) % P for i in range(1, W)]
+    for r in range(26, 30):
+        y = [sbox(t) for t in x]
+        x = [(sum(mds[i][j] * y[j] for j in range(W)) + (rc[r + 1][i] if r < 29 else 0)) % P for i in range(W)]
+    return x
+
+
 def _states(n, seed):
     s = uniform_states(n, seed=seed).astype(object).tolist()
     edge = [int(e) for e in EDGE_WORDS]
@@ -64,6 +90,7 @@ def test_sparse_form_equals_textbook_seeded():
     want = oracle.permute(oracle.Params(rc, mds), np.array(states, dtype=np.uint64))
     for st, w in zip(states, want):
         assert sparse_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
+        assert paired_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
 
 
 @pytest.mark.parametrize("name", ["identity", "const"])
@@ -76,6 +103,17 @@ def test_sparse_form_equals_textbook_special(name):
     want = oracle.permute(oracle.Params(rc, mds), np.array(states, dtype=np.uint64))
     for st, w in zip(states, want):
         assert sparse_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
+        assert paired_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
+
+
+def test_beta_mistake_is_caught():
+    # A wrong pairing scalar changes the paired permutation.
+    rc, mds = load_constants()
+    sp = gc.sparse_form(rc, mds)
+    st = [int(v) for v in _states(1, seed=42)[0]]
+    good = paired_permute(st, rc, mds, sp)
+    sp["beta"] = [sp["beta"][0]] + [(b + 1) % P for b in sp["beta"][1:]]
+    assert paired_permute(st, rc, mds, sp) != good
 
 
 def test_sparse_form_absent_when_block_singular():
