@@ -201,8 +201,12 @@ int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint6
     }
     if (int rc = blocks_for(n_rows, 1, &g)) return rc;
     return timed_launch("leaf_hash", st, [&] {
-        hipLaunchKernelGGL(goldi::k_leaf_hash, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols, digests,
-                           status);
+        if (n_cols <= goldi::RATE)
+            hipLaunchKernelGGL(goldi::k_leaf_hash<true>, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
+                               digests, status);
+        else
+            hipLaunchKernelGGL(goldi::k_leaf_hash<false>, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
+                               digests, status);
     });
 }
 
@@ -276,18 +280,21 @@ int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, ui
     memset(&b, 0, sizeof b);
     b.n_trees = nt;
     size_t items[goldi::MAX_BATCH];
-    size_t total = 0;
+    size_t total = 0, max_cols = 0;
     for (uint32_t k = 0; k < nt; k++) {
         const goldi_tree_t &T = trees[order[k]];
         b.t[k] = {T.leaves, T.nodes_out, (uint32_t)T.n_rows, (uint32_t)T.n_cols};
         items[k] = T.n_rows;
         total += T.n_rows;
+        max_cols = std::max(max_cols, T.n_cols);
     }
     int rc = total <= l12_max_rows()
                  ? launch_batch("leaf_hash_lane12", goldi::k_leaf_hash_lane12_batch, b, items, 16, st, status)
              : total <= quad_max_rows()
                  ? launch_batch("leaf_hash_quad", goldi::k_leaf_hash_quad_batch, b, items, 4, st, status)
-                 : launch_batch("leaf_hash", goldi::k_leaf_hash_batch, b, items, 1, st, status);
+                 : max_cols <= goldi::RATE
+                 ? launch_batch("leaf_hash", goldi::k_leaf_hash_batch<true>, b, items, 1, st, status)
+                 : launch_batch("leaf_hash", goldi::k_leaf_hash_batch<false>, b, items, 1, st, status);
     if (rc) return rc;
     // Level loop: off[k] = first node of the current child level of tree k.
     std::vector<size_t> off(nt, 0), n(nt);

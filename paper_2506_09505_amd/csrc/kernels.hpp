@@ -38,22 +38,38 @@ __device__ __forceinline__ void store_digest(u64 *dst, const u64 s[WIDTH]) {
 // Leaf linear hash of row r (Sec. 2.4 sponge, Sec. 4.2 leaves): the row of
 // the column-major matrix is absorbed in chunks of 8 words; lane r reads
 // leaves[c*n_rows + r], so a wave's loads of one column are contiguous.
+// SINGLE: the caller guarantees n_cols <= 8, so the row is one absorption of
+// a zero-capacity state and only the digest is kept (the permutation skips
+// the constant S-boxes of round 0 and rows 4..11 of the last matrix).
+template <bool SINGLE>
 __device__ __forceinline__ void leaf_row(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
                                          u64 *__restrict__ digests, uint32_t *status, size_t r) {
     u64 s[WIDTH];
 #pragma unroll
     for (int k = 0; k < WIDTH; k++) s[k] = 0;
     bool bad = false;
-    for (size_t c0 = 0; c0 < n_cols; c0 += RATE) {
+    if constexpr (SINGLE) {
 #pragma unroll
         for (int k = 0; k < RATE; k++) {
-            if (c0 + k < n_cols) {
-                const u64 w = leaves[(c0 + k) * n_rows + r];
+            if (k < (int)n_cols) {
+                const u64 w = leaves[(size_t)k * n_rows + r];
                 bad |= w >= P;
-                s[k] = add_weak(s[k], w);
+                s[k] = w;
             }
         }
-        permute(s);
+        permute(s, true, true);
+    } else {
+        for (size_t c0 = 0; c0 < n_cols; c0 += RATE) {
+#pragma unroll
+            for (int k = 0; k < RATE; k++) {
+                if (c0 + k < n_cols) {
+                    const u64 w = leaves[(c0 + k) * n_rows + r];
+                    bad |= w >= P;
+                    s[k] = add_weak(s[k], w);
+                }
+            }
+            permute(s);
+        }
     }
     report(status, bad);
     store_digest(digests + r * DIGEST, s);
@@ -71,7 +87,7 @@ __device__ __forceinline__ void level_node(const u64 *__restrict__ child, size_t
         for (int k = 0; k < 2 * DIGEST; k++) s[k] = c[k];
 #pragma unroll
         for (int k = 2 * DIGEST; k < WIDTH; k++) s[k] = 0;
-        permute(s);
+        permute(s, true, true);
         store_digest(parent + i * DIGEST, s);
     } else {
 #pragma unroll
@@ -186,10 +202,11 @@ __global__ void GOLDI_KERNEL_ATTRS k_permute(u64 *states, size_t n, uint32_t *st
     for (int k = 0; k < WIDTH; k++) p[k] = canon(s[k]);
 }
 
+template <bool SINGLE>
 __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
                                                u64 *__restrict__ digests, uint32_t *status) {
     const size_t r = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (r < n_rows) leaf_row(leaves, n_rows, n_cols, digests, status, r);
+    if (r < n_rows) leaf_row<SINGLE>(leaves, n_rows, n_cols, digests, status, r);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level(const u64 *__restrict__ child, size_t n_child, u64 *__restrict__ parent) {
@@ -264,10 +281,11 @@ __device__ __forceinline__ int batch_tree_of(const Batch &b, uint32_t blk) {
     return lo;
 }
 
+template <bool SINGLE>
 __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_batch(const Batch b, uint32_t *status) {
     const int t = batch_tree_of(b, blockIdx.x);
     const size_t r = (size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x;
-    if (r < b.t[t].n) leaf_row(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r);
+    if (r < b.t[t].n) leaf_row<SINGLE>(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad_batch(const Batch b, uint32_t *status) {

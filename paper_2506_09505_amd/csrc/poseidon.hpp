@@ -40,6 +40,11 @@ static constexpr int ROUNDS = 2 * HALF_FULL + PARTIAL;
 // Round constants, split into 32-bit halves held in 64-bit words (see the
 // generator); row ROUNDS is zero.
 __constant__ u64 RC_SPLIT[ROUNDS + 1][WIDTH][2] = GOLDI_RC_SPLIT_INIT;
+// For a state whose words 8..11 are zero (a sponge's first absorption, a tree
+// node): those words enter round 0 as C[0][8..11], so their S-box outputs
+// and matrix terms are constants; row i's constant becomes
+// C[1][i] + sum_k M[i][8+k] C[0][8+k]^7 (mod p), split like RC_SPLIT.
+__constant__ u64 CAP0_RC1[WIDTH][2] = GOLDI_CAP0_RC1_INIT;
 
 __device__ __forceinline__ u64 sbox(u64 x) {
     const u64 x2 = sqr(x);
@@ -96,46 +101,49 @@ __device__ __forceinline__ u64 mad_small_sacc(u32 x, u64 acc) {
 // Terms are accumulated for words 1..11 first and word 0 last: in a partial
 // round only word 0 went through the S-box, so the other eleven products can
 // issue while its S-box chain is still running.
-template <int I, int K>
+// Row I over the words 1 .. NW-1 and then 0 (NW = 12: all words; NW = 8:
+// the words of a state whose words 8..11 enter as a constant instead).
+template <int I, int K, int NW = WIDTH>
 __device__ __forceinline__ void mds_term(const u64 s[WIDTH], u64 &a_lo, u64 &a_hi) {
-    constexpr int J = (K + 1) % WIDTH;
+    constexpr int J = (K + 1) % NW;
     a_lo = mad_small<GOLDI_MDS[I][J]>(lo32(s[J]), a_lo);
     a_hi = mad_small<GOLDI_MDS[I][J]>(hi32(s[J]), a_hi);
-    if constexpr (K + 1 < WIDTH) mds_term<I, K + 1>(s, a_lo, a_hi);
+    if constexpr (K + 1 < NW) mds_term<I, K + 1, NW>(s, a_lo, a_hi);
 }
 
-template <int I, int END>
+template <int I, int END, int NW = WIDTH>
 __device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], const u64 (*rc)[2]) {
     constexpr int J = 1;  // the first word of mds_term's order
     u64 a_lo = mad_small_sacc<GOLDI_MDS[I][J]>(lo32(s[J]), rc[I][0]);
     u64 a_hi = mad_small_sacc<GOLDI_MDS[I][J]>(hi32(s[J]), rc[I][1]);
-    mds_term<I, 1>(s, a_lo, a_hi);
+    mds_term<I, 1, NW>(s, a_lo, a_hi);
     out[I] = reduce_split(a_lo, a_hi);
-    if constexpr (I + 1 < END) mds_rows<I + 1, END>(s, out, rc);
+    if constexpr (I + 1 < END) mds_rows<I + 1, END, NW>(s, out, rc);
 }
 
 #ifndef GOLDI_RC_GROUP
 #define GOLDI_RC_GROUP 6  // rows per batch of round-constant loads
 #endif
 
-template <int I0>
-__device__ __forceinline__ void mds_row_group(const u64 s[WIDTH], u64 out[WIDTH], int r1) {
+// Rows I0..11 with the per-row constants tbl[i] (split as in RC_SPLIT).
+template <int I0, int NW = WIDTH>
+__device__ __forceinline__ void mds_row_group(const u64 s[WIDTH], u64 out[WIDTH], const u64 (*tbl)[2]) {
     constexpr int I1 = I0 + GOLDI_RC_GROUP < WIDTH ? I0 + GOLDI_RC_GROUP : WIDTH;
     u64 rc[WIDTH][2];
 #pragma unroll
     for (int i = I0; i < I1; i++) {
-        rc[i][0] = RC_SPLIT[r1][i][0];
-        rc[i][1] = RC_SPLIT[r1][i][1];
+        rc[i][0] = tbl[i][0];
+        rc[i][1] = tbl[i][1];
     }
-    mds_rows<I0, I1>(s, out, rc);
-    if constexpr (I1 < WIDTH) mds_row_group<I1>(s, out, r1);
+    mds_rows<I0, I1, NW>(s, out, rc);
+    if constexpr (I1 < WIDTH) mds_row_group<I1, NW>(s, out, tbl);
 }
 
 // s <- M s + C[r1]  (C[ROUNDS] = 0).  The constants of a group of rows are
 // read together (wave-uniform scalar loads), so one wait covers the group.
 __device__ __forceinline__ void mds_add_rc(u64 s[WIDTH], int r1) {
     u64 out[WIDTH];
-    mds_row_group<0>(s, out, r1);
+    mds_row_group<0>(s, out, RC_SPLIT[r1]);
 #pragma unroll
     for (int i = 0; i < WIDTH; i++) s[i] = out[i];
 }
@@ -239,8 +247,7 @@ __device__ __forceinline__ u64 col_update2(u64 z, const u64 (&sh)[3], const u32 
 
 // The last opening full round's matrix with the pre-matrix folded in:
 // row 0 is M's (plus the scalar k_4), rows 1..11 are diag(1, Mh^22) M.
-__device__ __forceinline__ void pre_matrix(u64 s[WIDTH]) {
-    u64 out[WIDTH];
+__device__ __forceinline__ void pre_matrix(const u64 s[WIDTH], u64 out[WIDTH]) {
     const u64 k4[1][2] = {GOLDI_SP_K4_SPLIT};
     mds_rows<0, 1>(s, out, k4);
     // Rows 1..11 one per iteration of a rolled loop (the scalar registers
@@ -257,8 +264,6 @@ __device__ __forceinline__ void pre_matrix(u64 s[WIDTH]) {
         for (int k = 1; k < WIDTH - 1; k++) out[k] = out[k + 1];
         out[WIDTH - 1] = dot_finish(d);
     }
-#pragma unroll
-    for (int i = 0; i < WIDTH; i++) s[i] = out[i];
 }
 
 // Partial rounds HALF_FULL + j and HALF_FULL + j + 1 (j even).  With a and b
@@ -297,34 +302,63 @@ __device__ __forceinline__ void partial_round(u64 s[WIDTH], int r) {
 }
 
 // In place; input words must be < 2^64 (any word), output words are weak.
-__device__ __forceinline__ void permute(u64 s[WIDTH]) {
+// cap0: the caller guarantees words 8..11 are zero (they are not read);
+// digest_only: only words 0..3 of the output are used (4..11 are left stale).
+// Both are wave-uniform; call sites with constant flags compile to one path.
+__device__ __forceinline__ void permute(u64 s[WIDTH], bool cap0 = false, bool digest_only = false) {
+    const int n_in = cap0 ? 2 * DIGEST : WIDTH;
 #pragma unroll
-    for (int i = 0; i < WIDTH; i++) s[i] = add_weak(s[i], mk64(lo32(RC_SPLIT[0][i][0]), lo32(RC_SPLIT[0][i][1])));
+    for (int i = 0; i < WIDTH; i++)
+        if (i < n_in) s[i] = add_weak(s[i], mk64(lo32(RC_SPLIT[0][i][0]), lo32(RC_SPLIT[0][i][1])));
 #ifndef GOLDI_PARTIAL_UNROLL
 #define GOLDI_PARTIAL_UNROLL 2
 #endif
-#if GOLDI_USE_SPARSE
+    // Opening full rounds.  Round 0 of a zero-capacity state: S-boxes of
+    // words 0..7 only, and the matrix over those words with CAP0_RC1.
 #pragma nounroll
     for (int r = 0; r < HALF_FULL; r++) {
+        const bool short0 = cap0 && r == 0;
 #pragma unroll
-        for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
-        if (r + 1 < HALF_FULL)
-            mds_add_rc(s, r + 1);
+        for (int i = 0; i < WIDTH; i++)
+            if (i < 2 * DIGEST || !short0) s[i] = sbox(s[i]);
+        u64 out[WIDTH];
+        if (short0)
+            mds_row_group<0, 2 * DIGEST>(s, out, CAP0_RC1);
+#if GOLDI_USE_SPARSE
+        else if (r + 1 == HALF_FULL)
+            pre_matrix(s, out);
+#endif
         else
-            pre_matrix(s);
+            mds_row_group<0>(s, out, RC_SPLIT[r + 1]);
+#pragma unroll
+        for (int i = 0; i < WIDTH; i++) s[i] = out[i];
     }
+#if GOLDI_USE_SPARSE
 #pragma nounroll
     for (int j = 0; j < PARTIAL; j += 2) sparse_pair(s, j);
 #pragma unroll
     for (int i = 1; i < WIDTH; i++) s[i] = add_weak(s[i], mk64(SP_CEND[i - 1][0], SP_CEND[i - 1][1]));
 #else
-#pragma nounroll
-    for (int r = 0; r < HALF_FULL; r++) full_round(s, r);
 #pragma unroll GOLDI_PARTIAL_UNROLL
     for (int r = HALF_FULL; r < HALF_FULL + PARTIAL; r++) partial_round(s, r);
 #endif
+    // Closing full rounds; with digest_only the last matrix computes rows
+    // 0..3 only.
 #pragma nounroll
-    for (int r = HALF_FULL + PARTIAL; r < ROUNDS; r++) full_round(s, r);
+    for (int r = HALF_FULL + PARTIAL; r < ROUNDS; r++) {
+#pragma unroll
+        for (int i = 0; i < WIDTH; i++) s[i] = sbox(s[i]);
+        u64 out[WIDTH];
+        if (digest_only && r + 1 == ROUNDS) {
+            mds_rows<0, DIGEST>(s, out, RC_SPLIT[ROUNDS]);
+#pragma unroll
+            for (int i = 0; i < DIGEST; i++) s[i] = out[i];
+        } else {
+            mds_row_group<0>(s, out, RC_SPLIT[r + 1]);
+#pragma unroll
+            for (int i = 0; i < WIDTH; i++) s[i] = out[i];
+        }
+    }
 }
 
 }  // namespace goldi

@@ -179,7 +179,16 @@ def render(spec: dict, source: str = "synth/poseidon12.json") -> str:
         cells = ", ".join("{0x%08xull, 0x%08xull}" % (v & 0xFFFFFFFF, v >> 32) for v in row)
         lines.append("    {%s}, \\" % cells)
     lines.append("}")
-    lines.extend(render_sparse([[int(v) for v in row] for row in spec["rc"]], [[int(v) for v in row] for row in mds]))
+    rc_int = [[int(v) for v in row] for row in spec["rc"]]
+    mds_int = [[int(v) for v in row] for row in mds]
+    # A state whose words 8..11 are zero: their round-0 S-box outputs are
+    # constants, folded with their matrix terms into row i's next constant.
+    caps = [pow(rc_int[0][8 + k], 7, P) for k in range(4)]
+    r1 = [(rc_int[1][i] + sum(mds_int[i][8 + k] * caps[k] for k in range(4))) % P for i in range(12)]
+    lines.append("// GOLDI_CAP0_RC1[i]: C[1][i] + sum_k M[i][8+k] C[0][8+k]^7 (mod p), split as above.")
+    lines.append("#define GOLDI_CAP0_RC1_INIT {%s}" % ", ".join("{0x%08xull, 0x%08xull}" % (v & 0xFFFFFFFF, v >> 32)
+                                                              for v in r1))
+    lines.extend(render_sparse(rc_int, mds_int))
     return "\n".join(lines) + "\n"
 
 
