@@ -165,10 +165,10 @@ __device__ __forceinline__ void full_round(u64 s[WIDTH], int r) {
 // Full-width entries come as three 22-bit limbs, so each 32 x 22-bit product
 // is below 2^54 and the dozen terms of a dot product add up in six 64-bit
 // accumulators without carries; they are combined once.  Rounds go in
-// pairs: the second dot product reads the words from before the first
-// round's column update (plus a precomputed scalar times the first S-box
-// output), so each word takes both rounds' column terms in one reduction,
-// from the constant limbs times s, s 2^22 and s 2^44 (mod p).
+// groups: a later round's dot product reads the words from the start of the
+// group (plus precomputed scalars times the group's earlier S-box outputs),
+// so each word takes all the group's column terms in one reduction, from the
+// constant limbs times s, s 2^22 and s 2^44 (mod p).
 #ifndef GOLDI_PARTIAL_SPARSE
 #define GOLDI_PARTIAL_SPARSE 1
 #endif
@@ -178,7 +178,7 @@ __constant__ u32 SP_K[PARTIAL + 1][3] = GOLDI_SP_K_INIT;
 __constant__ u32 SP_CEND[WIDTH - 1][2] = GOLDI_SP_CEND_INIT;
 __constant__ u32 SP_ROW[PARTIAL][WIDTH - 1][3] = GOLDI_SP_ROW_INIT;
 __constant__ u32 SP_COL22[PARTIAL][WIDTH - 1][3] = GOLDI_SP_COL22_INIT;
-__constant__ u32 SP_BETA[PARTIAL / 2][3] = GOLDI_SP_BETA_INIT;
+__constant__ u32 SP_LAG[PARTIAL][3][3] = GOLDI_SP_LAG_INIT;
 __constant__ u32 SP_PRE_M[WIDTH - 1][WIDTH][3] = GOLDI_SP_PRE_M_INIT;
 #else
 #define GOLDI_USE_SPARSE 0
@@ -224,23 +224,22 @@ __device__ __forceinline__ u64 dot_finish(const Dot6 &d) {
 // r 2^22 mod p as a weak word.
 __device__ __forceinline__ u64 shl22(u64 r) { return mad_eps_fold(hi32(r) >> 10, r << 22); }
 
-// z + c s + e t (mod p) for constants c, e in 22-bit limbs g, e and
-// sh = {s, s 2^22, s 2^44}, th = {t, t 2^22, t 2^44} (mod p): twelve
-// 32 x 22-bit products into a low and a high accumulator (each below
-// 6 2^54 + 2^32), then one split reduction.
-__device__ __forceinline__ u64 col_update2(u64 z, const u64 (&sh)[3], const u32 (&g)[3], const u64 (&th)[3],
-                                           const u32 (&e)[3]) {
-    u64 a_lo = mad32(lo32(sh[0]), g[0], (u64)lo32(z));
-    u64 a_hi = mad32(hi32(sh[0]), g[0], (u64)hi32(z));
+// z + sum_g c_g x_g (mod p) for G constants c_g (22-bit limbs of the
+// first-column entries of partial rounds j .. j+G-1 for word i) and
+// sh[g] = {x_g, x_g 2^22, x_g 2^44} (mod p): 6 G products of 32 x 22 bits
+// into a low and a high accumulator (each below 3 G 2^54 + 2^32), then one
+// split reduction.
+template <int G>
+__device__ __forceinline__ u64 col_update(u64 z, const u64 (&sh)[G][3], int j, int i) {
+    u64 a_lo = mad32(lo32(sh[0][0]), SP_COL22[j][i][0], (u64)lo32(z));
+    u64 a_hi = mad32(hi32(sh[0][0]), SP_COL22[j][i][0], (u64)hi32(z));
 #pragma unroll
-    for (int j = 1; j < 3; j++) {
-        a_lo = mad32(lo32(sh[j]), g[j], a_lo);
-        a_hi = mad32(hi32(sh[j]), g[j], a_hi);
-    }
+    for (int g = 0; g < G; g++) {
 #pragma unroll
-    for (int j = 0; j < 3; j++) {
-        a_lo = mad32(lo32(th[j]), e[j], a_lo);
-        a_hi = mad32(hi32(th[j]), e[j], a_hi);
+        for (int l = (g == 0 ? 1 : 0); l < 3; l++) {
+            a_lo = mad32(lo32(sh[g][l]), SP_COL22[j + g][i][l], a_lo);
+            a_hi = mad32(hi32(sh[g][l]), SP_COL22[j + g][i][l], a_hi);
+        }
     }
     return reduce_split(a_lo, a_hi);
 }
@@ -266,34 +265,40 @@ __device__ __forceinline__ void pre_matrix(const u64 s[WIDTH], u64 out[WIDTH]) {
     }
 }
 
-// Partial rounds HALF_FULL + j and HALF_FULL + j + 1 (j even).  With a and b
-// the two S-box outputs, the second dot product reads the words before the
-// first column update plus beta a, and each word takes both column terms in
-// one reduction:  x_i += col_j[i] a + col_(j+1)[i] b.
-__device__ __forceinline__ void sparse_pair(u64 s[WIDTH], int j) {
-    const u64 xa = sbox(s[0]);
-    Dot6 d;
-    dot_init(d, SP_K[j + 1]);
-    d.a0[0] = mad_small<GOLDI_MDS[0][0]>(lo32(xa), d.a0[0]);
-    d.a1[0] = mad_small<GOLDI_MDS[0][0]>(hi32(xa), d.a1[0]);
+// Partial rounds HALF_FULL + j .. HALF_FULL + j + G - 1.  With x_g the
+// S-box output of round g of the group, round g's dot product reads the words
+// from the start of the group plus sum_h lag * x_h over the group's earlier
+// rounds, and each word takes all G column terms in one reduction:
+//   x_i += sum_g col_(j+g)[i] x_g.
+template <int G>
+__device__ __forceinline__ void sparse_group(u64 s[WIDTH], int j) {
+    u64 x[G];
+    x[0] = sbox(s[0]);
 #pragma unroll
-    for (int i = 1; i < WIDTH; i++) dot_term(d, s[i], SP_ROW[j][i - 1]);
-    const u64 xb = sbox(dot_finish(d));
-    Dot6 e;
-    dot_init(e, SP_K[j + 2]);
-    e.a0[0] = mad_small<GOLDI_MDS[0][0]>(lo32(xb), e.a0[0]);
-    e.a1[0] = mad_small<GOLDI_MDS[0][0]>(hi32(xb), e.a1[0]);
+    for (int g = 0; g < G; g++) {
+        Dot6 d;
+        dot_init(d, SP_K[j + g + 1]);
+        d.a0[0] = mad_small<GOLDI_MDS[0][0]>(lo32(x[g]), d.a0[0]);
+        d.a1[0] = mad_small<GOLDI_MDS[0][0]>(hi32(x[g]), d.a1[0]);
 #pragma unroll
-    for (int i = 1; i < WIDTH; i++) dot_term(e, s[i], SP_ROW[j + 1][i - 1]);
-    dot_term(e, xa, SP_BETA[j / 2]);
-    const u64 a1 = shl22(xa), b1 = shl22(xb);
-    const u64 sa[3] = {xa, a1, shl22(a1)};
-    const u64 sb[3] = {xb, b1, shl22(b1)};
+        for (int i = 1; i < WIDTH; i++) dot_term(d, s[i], SP_ROW[j + g][i - 1]);
 #pragma unroll
-    for (int i = 1; i < WIDTH; i++) s[i] = col_update2(s[i], sa, SP_COL22[j][i - 1], sb, SP_COL22[j + 1][i - 1]);
-    s[0] = dot_finish(e);
+        for (int h = 0; h < g; h++) dot_term(d, x[h], SP_LAG[j + g][g - 1 - h]);
+        if (g + 1 < G)
+            x[g + 1] = sbox(dot_finish(d));
+        else
+            s[0] = dot_finish(d);
+    }
+    u64 sh[G][3];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        sh[g][0] = x[g];
+        sh[g][1] = shl22(x[g]);
+        sh[g][2] = shl22(sh[g][1]);
+    }
+#pragma unroll
+    for (int i = 1; i < WIDTH; i++) s[i] = col_update<G>(s[i], sh, j, i - 1);
 }
-
 #endif
 
 __device__ __forceinline__ void partial_round(u64 s[WIDTH], int r) {
@@ -334,8 +339,10 @@ __device__ __forceinline__ void permute(u64 s[WIDTH], bool cap0 = false, bool di
         for (int i = 0; i < WIDTH; i++) s[i] = out[i];
     }
 #if GOLDI_USE_SPARSE
+    // Pairs: larger groups measured slower (their constants no longer fit the
+    // scalar registers of one group).
 #pragma nounroll
-    for (int j = 0; j < PARTIAL; j += 2) sparse_pair(s, j);
+    for (int j = 0; j < PARTIAL; j += 2) sparse_group<2>(s, j);
 #pragma unroll
     for (int i = 1; i < WIDTH; i++) s[i] = add_weak(s[i], mk64(SP_CEND[i - 1][0], SP_CEND[i - 1][1]));
 #else

@@ -114,11 +114,12 @@ def sparse_form(rc, mds, half_full: int = 4, partial: int = 22):
         k.append(d[0])
         carry = _mv(mds, [0] + d[1:])
     c_end = [(rc[half_full + partial][i] + carry[i]) % P for i in range(w12)]
-    # Two partial rounds at a time: the second round's dot product can use the
-    # words before the first round's column update, plus beta times the first
-    # round's S-box output, with beta = <row of the second, col of the first>.
-    beta = [sum(row[j + 1][i] * col[j][i] for i in range(w12 - 1)) % P for j in range(0, partial - 1, 2)]
-    return {"k": k, "c_end": c_end, "row": row, "col": col, "pre": pre, "pre_m": pre_m, "beta": beta}
+    # Partial rounds in groups: a later round's dot product can use the words
+    # from the start of its group, plus lag[r][d] times the S-box output of
+    # round r - 1 - d of the same group, lag[r][d] = <row of r, col of r-1-d>.
+    lag = [[sum(row[r][i] * col[r - 1 - d][i] for i in range(w12 - 1)) % P if r - 1 - d >= 0 else 0
+            for d in range(3)] for r in range(partial)]
+    return {"k": k, "c_end": c_end, "row": row, "col": col, "pre": pre, "pre_m": pre_m, "lag": lag}
 
 
 def _limbs22(x: int):
@@ -136,7 +137,7 @@ def render_sparse(rc, mds) -> list:
     if sp is None:
         lines.append("#define GOLDI_SPARSE_OK 0  // the lower-right 11 x 11 block of M is singular")
         sp = {"k": [0] * 22, "c_end": [0] * 12, "row": [[0] * 11] * 22, "col": [[0] * 11] * 22,
-              "pre_m": [[0] * 12] * 11, "beta": [0] * 11}
+              "pre_m": [[0] * 12] * 11, "lag": [[0] * 3] * 22}
     else:
         lines.append("#define GOLDI_SPARSE_OK 1")
     k = sp["k"] + [sp["c_end"][0]]
@@ -148,8 +149,8 @@ def render_sparse(rc, mds) -> list:
     lines.append(_c_array("GOLDI_SP_ROW", "u32", [22, 11, 3], [l for r in sp["row"] for x in r for l in _limbs22(x)]))
     lines.append("// GOLDI_SP_COL22[j][i]: 22-bit limbs of first-column entry i+1 of partial round 4+j.")
     lines.append(_c_array("GOLDI_SP_COL22", "u32", [22, 11, 3], [l for r in sp["col"] for x in r for l in _limbs22(x)]))
-    lines.append("// GOLDI_SP_BETA[q]: 22-bit limbs of <row of round 4+2q+1, col of round 4+2q>.")
-    lines.append(_c_array("GOLDI_SP_BETA", "u32", [11, 3], [l for x in sp["beta"] for l in _limbs22(x)]))
+    lines.append("// GOLDI_SP_LAG[j][d]: 22-bit limbs of <row of round 4+j, col of round 4+j-1-d>.")
+    lines.append(_c_array("GOLDI_SP_LAG", "u32", [22, 3, 3], [l for r in sp["lag"] for x in r for l in _limbs22(x)]))
     lines.append("// GOLDI_SP_PRE_M[i][j]: 22-bit limbs of row i+1, column j of diag(1, Mh^22) M.")
     lines.append(_c_array("GOLDI_SP_PRE_M", "u32", [11, 12, 3], [l for r in sp["pre_m"] for x in r for l in _limbs22(x)]))
     k4 = sp["k"][0]

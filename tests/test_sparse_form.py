@@ -48,11 +48,11 @@ def sparse_permute(x, rc, mds, sp):
     return x
 
 
-def paired_permute(x, rc, mds, sp):
-    """The same with partial rounds in pairs, as the kernels take them: the
-    second dot product uses the words from before the first column update
-    plus beta times the first S-box output; both column terms are added at
-    once."""
+def grouped_permute(x, rc, mds, sp, groups):
+    """The same with the partial rounds in groups (sizes `groups`, summing to
+    22), as the kernels take them: round g of a group reads the words from the
+    start of the group plus lag terms times the group's earlier S-box
+    outputs; each word then takes all of the group's column terms at once."""
     x = [(x[i] + rc[0][i]) % P for i in range(W)]
     for r in range(3):
         y = [sbox(t) for t in x]
@@ -60,18 +60,27 @@ def paired_permute(x, rc, mds, sp):
     y = [sbox(t) for t in x]
     x = [(sum(mds[0][j] * y[j] for j in range(W)) + sp["k"][0]) % P]
     x += [sum(sp["pre_m"][i][j] * y[j] for j in range(W)) % P for i in range(W - 1)]
-    for j in range(0, 22, 2):
-        a = sbox(x[0])
-        b = sbox((mds[0][0] * a + sum(sp["row"][j][i] * x[i + 1] for i in range(W - 1)) + sp["k"][j + 1]) % P)
-        nxt = sp["k"][j + 2] if j + 2 < 22 else sp["c_end"][0]
-        x0 = (mds[0][0] * b + sum(sp["row"][j + 1][i] * x[i + 1] for i in range(W - 1))
-              + sp["beta"][j // 2] * a + nxt) % P
-        x = [x0] + [(x[i + 1] + sp["col"][j][i] * a + sp["col"][j + 1][i] * b) % P for i in range(W - 1)]
+    j = 0
+    for gsize in groups:
+        outs = [sbox(x[0])]
+        for g in range(gsize):
+            r = j + g
+            nxt = sp["k"][r + 1] if r + 1 < 22 else sp["c_end"][0]
+            d0 = (mds[0][0] * outs[g] + sum(sp["row"][r][i] * x[i + 1] for i in range(W - 1))
+                  + sum(sp["lag"][r][g - 1 - h] * outs[h] for h in range(g)) + nxt) % P
+            if g + 1 < gsize:
+                outs.append(sbox(d0))
+        x = [d0] + [(x[i + 1] + sum(sp["col"][j + g][i] * outs[g] for g in range(gsize))) % P for i in range(W - 1)]
+        j += gsize
+    assert j == 22
     x = [x[0]] + [(x[i] + sp["c_end"][i]) % P for i in range(1, W)]
     for r in range(26, 30):
         y = [sbox(t) for t in x]
         x = [(sum(mds[i][j] * y[j] for j in range(W)) + (rc[r + 1][i] if r < 29 else 0)) % P for i in range(W)]
     return x
+
+
+GROUPINGS = [[1] * 22, [2] * 11, [4] * 5 + [2], [3] * 6 + [4]]
 
 
 def _states(n, seed):
@@ -90,7 +99,8 @@ def test_sparse_form_equals_textbook_seeded():
     want = oracle.permute(oracle.Params(rc, mds), np.array(states, dtype=np.uint64))
     for st, w in zip(states, want):
         assert sparse_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
-        assert paired_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
+        for groups in GROUPINGS:
+            assert grouped_permute([int(v) for v in st], rc, mds, sp, groups) == [int(v) for v in w]
 
 
 @pytest.mark.parametrize("name", ["identity", "const"])
@@ -103,17 +113,21 @@ def test_sparse_form_equals_textbook_special(name):
     want = oracle.permute(oracle.Params(rc, mds), np.array(states, dtype=np.uint64))
     for st, w in zip(states, want):
         assert sparse_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
-        assert paired_permute([int(v) for v in st], rc, mds, sp) == [int(v) for v in w]
+        for groups in GROUPINGS:
+            assert grouped_permute([int(v) for v in st], rc, mds, sp, groups) == [int(v) for v in w]
 
 
-def test_beta_mistake_is_caught():
-    # A wrong pairing scalar changes the paired permutation.
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_lag_mistake_is_caught(d):
+    # A wrong lag scalar changes the grouped permutation.
     rc, mds = load_constants()
     sp = gc.sparse_form(rc, mds)
     st = [int(v) for v in _states(1, seed=42)[0]]
-    good = paired_permute(st, rc, mds, sp)
-    sp["beta"] = [sp["beta"][0]] + [(b + 1) % P for b in sp["beta"][1:]]
-    assert paired_permute(st, rc, mds, sp) != good
+    groups = [4] * 5 + [2]
+    good = grouped_permute(st, rc, mds, sp, groups)
+    sp["lag"] = [list(r) for r in sp["lag"]]
+    sp["lag"][7][d] = (sp["lag"][7][d] + 1) % P  # round 7 is the fourth of its group
+    assert grouped_permute(st, rc, mds, sp, groups) != good
 
 
 def test_sparse_form_absent_when_block_singular():
