@@ -299,8 +299,18 @@ def bench_batch(args) -> int:
     goldi.goldi_profile_enable(True)
     ms = timed(run_many, args.steps)
     goldi.goldi_profile_enable(False)
-    goldi.goldi_profile_select(None)
     leaf_tot, leaf_cnt = goldi.goldi_profile_read("leaf_hash")
+    leaf_note = "timed inside the measured builds"
+    if leaf_cnt == 0:
+        # A replayed hipGraph records no per-kernel events: time the dominant
+        # kernel in the same schedule launched directly.
+        goldi.goldi_tune_set("graph", 0)
+        goldi.goldi_profile_enable(True)
+        timed(run_many, max(2, args.steps // 2))
+        goldi.goldi_profile_enable(False)
+        leaf_tot, leaf_cnt = goldi.goldi_profile_read("leaf_hash")
+        leaf_note = "tuned schedule replays a hipGraph; kernel timed in the same schedule launched directly"
+    goldi.goldi_profile_select(None)
     exact = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(outs, plain))
     autotune.apply(saved)
     if int(status.item()) != 0:
@@ -321,7 +331,7 @@ def bench_batch(args) -> int:
                      "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_MULADD_PER_S / 1e12, 3),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_MULADD_PER_S, 4),
                      "op": OP_TEXT,
-                     "kernel_ms": round(leaf_ms, 4), "traffic": None},
+                     "kernel_ms": round(leaf_ms, 4), "kernel_timing": leaf_note, "traffic": None},
     }
     print(json.dumps(out), flush=True)
     return 0 if exact else 1

@@ -24,6 +24,7 @@ Apart from ``sparse_form`` the script only reformats.
 from __future__ import annotations
 
 import json
+import math
 import os
 
 P = (1 << 64) - (1 << 32) + 1
@@ -127,8 +128,17 @@ def _limbs22(x: int):
 
 
 def _c_array(name: str, ctype: str, dims, flat) -> str:
-    body = ", ".join("0x%xu" % v for v in flat)
-    return "#define %s_INIT {%s}  /* %s%s */" % (name, body, ctype, "".join("[%d]" % d for d in dims))
+    """A nested brace initializer for an array of shape dims from row-major values."""
+    flat = list(flat)
+    assert len(flat) == math.prod(dims)
+
+    def nest(vals, shape):
+        if len(shape) == 1:
+            return "{" + ", ".join("0x%xu" % v for v in vals) + "}"
+        step = len(vals) // shape[0]
+        return "{" + ", ".join(nest(vals[i * step:(i + 1) * step], shape[1:]) for i in range(shape[0])) + "}"
+
+    return "#define %s_INIT %s  /* %s%s */" % (name, nest(flat, dims), ctype, "".join("[%d]" % d for d in dims))
 
 
 def render_sparse(rc, mds) -> list:
