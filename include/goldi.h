@@ -120,6 +120,10 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
  *                      at or below these sizes one state word per lane (a
  *                      16-lane row per state) is used instead: lower latency
  *                      again, more instructions in total;
+ *   "top_max_parents"  single-tree builds run every level from the first one
+ *                      of at most this many parents up to the root in one
+ *                      single-workgroup launch (default 16, at most 64;
+ *                      0 = one launch per level; GOLDI_EINVAL above 64);
  *   "batch_mode"       goldi_merkle_build_many: 1 (default) = one launch per
  *                      tree level across all trees (up to 64 trees per
  *                      launch, heaviest rows first), 0 = tree after tree;

@@ -177,6 +177,11 @@ std::atomic<size_t> g_graph_mode{env_size("GOLDI_GRAPH_MODE", 0)};
 // latency still, more instructions in total).
 std::atomic<size_t> g_l12_max_rows{env_size("GOLDI_LANE12_MAX_ROWS", (size_t)1 << 12)};
 std::atomic<size_t> g_l12_max_parents{env_size("GOLDI_LANE12_MAX_PARENTS", (size_t)1 << 12)};
+// Single-tree builds finish in one launch (k_top_lane12) from the first level
+// of at most this many parents (<= 64; the default 16 keeps one wave per
+// SIMD of the workgroup's CU); 0 disables.
+std::atomic<size_t> g_top_max_parents{env_size("GOLDI_TOP_MAX_PARENTS", 16)};
+size_t top_max_parents() { return g_top_max_parents.load(std::memory_order_relaxed); }
 size_t l12_max_rows() { return g_l12_max_rows.load(std::memory_order_relaxed); }
 size_t l12_max_parents() { return g_l12_max_parents.load(std::memory_order_relaxed); }
 size_t quad_max_rows() { return g_quad_max_rows.load(std::memory_order_relaxed); }
@@ -237,6 +242,12 @@ int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *
     if (rc) return rc;
     size_t off = 0, n = n_rows;
     while (n > 1) {
+        if ((n + 1) / 2 <= top_max_parents()) {
+            const unsigned threads = (unsigned)(64 * (((n + 1) / 2 + 3) / 4));  // whole waves of 4 states
+            return timed_launch("top_lane12", st, [&] {
+                hipLaunchKernelGGL(goldi::k_top_lane12, dim3(1), dim3(threads), 0, st, nodes, off, n);
+            });
+        }
         rc = launch_level(nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST, st);
         if (rc) return rc;
         off += n;
@@ -525,6 +536,10 @@ int goldi_tune_set(const char *key, size_t value) {
         g_l12_max_rows.store(value);
     } else if (strcmp(key, "lane12_max_parents") == 0) {
         g_l12_max_parents.store(value);
+    } else if (strcmp(key, "top_max_parents") == 0) {
+        if (value > (size_t)goldi::TOP_STATES)
+            return fail(GOLDI_EINVAL, "top_max_parents must be at most %d", goldi::TOP_STATES);
+        g_top_max_parents.store(value);
     } else if (strcmp(key, "batch_mode") == 0) {
         if (value > 1) return fail(GOLDI_EINVAL, "batch_mode must be 0 or 1");
         g_batch_mode.store(value);
@@ -547,6 +562,8 @@ int goldi_tune_get(const char *key, size_t *value) {
         *value = l12_max_rows();
     } else if (strcmp(key, "lane12_max_parents") == 0) {
         *value = l12_max_parents();
+    } else if (strcmp(key, "top_max_parents") == 0) {
+        *value = top_max_parents();
     } else if (strcmp(key, "batch_mode") == 0) {
         *value = g_batch_mode.load();
     } else if (strcmp(key, "graph") == 0) {

@@ -232,6 +232,46 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, s
 
 static constexpr int LANE12_PER_BLOCK = BLOCK / 16;  // states per block
 
+// The top of a tree in one launch: every level from a level of at most
+// 2 TOP_STATES nodes up to the root, in one workgroup of up to TOP_THREADS
+// threads (states of 16 lanes, one word per lane; the host sizes the
+// workgroup to the first level's parents, so that few waves share a SIMD).
+// A level's nodes pass to the next level through LDS (and are written to the
+// node array); a workgroup barrier separates levels, so the top costs one
+// permutation latency per level and a single launch.  Waves with no parent
+// in a level skip its permutation (the test is the same in all their lanes).
+static constexpr int TOP_THREADS = 1024;
+static constexpr int TOP_STATES = TOP_THREADS / 16;
+
+__global__ void __launch_bounds__(TOP_THREADS) k_top_lane12(u64 *nodes, size_t off, size_t n) {
+    __shared__ QuadRc tbl;
+    __shared__ u64 buf[2][2 * TOP_STATES * DIGEST];
+    quad_rc_load(tbl);
+    const Lane12 L = lane12_setup(tbl);
+    const int p = threadIdx.x >> 4;        // the state (parent) this lane works on
+    const int p_wave = (threadIdx.x >> 6) * 4;  // first state of this wave
+    for (size_t k = threadIdx.x; k < n * DIGEST; k += blockDim.x) buf[0][k] = nodes[off * DIGEST + k];
+    __syncthreads();
+    int cur = 0;
+    while (n > 1) {  // n is the same in every thread: all reach each barrier
+        const size_t n_par = (n + 1) / 2;
+        const bool valid = (size_t)p < n_par && L.i < WIDTH;
+        const bool pair = valid && 2 * (size_t)p + 1 < n;
+        const u64 *child = buf[cur];
+        u64 x = (pair && L.i < 2 * DIGEST) ? child[2 * p * DIGEST + L.i] : 0;
+        if ((size_t)p_wave < n_par) x = permute_lane12(x, L, tbl);  // whole waves only
+        if (valid && L.i < DIGEST) {
+            const u64 d = pair ? canon(x) : child[2 * p * DIGEST + L.i];
+            buf[cur ^ 1][p * DIGEST + L.i] = d;
+            nodes[(off + n + p) * DIGEST + L.i] = d;
+        }
+        __syncthreads();
+        off += n;
+        n = n_par;
+        cur ^= 1;
+    }
+}
+
 __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
                                                       u64 *__restrict__ digests, uint32_t *status) {
     __shared__ QuadRc tbl;

@@ -67,3 +67,8 @@ def test_tune_knobs_cpu():
     goldi.goldi_tune_set("quad_max_rows", old)
     with pytest.raises(goldi.GoldiError):
         goldi.goldi_tune_set("no_such_knob", 1)
+    top = goldi.goldi_tune_get("top_max_parents")
+    assert top == 16
+    with pytest.raises(goldi.GoldiError):
+        goldi.goldi_tune_set("top_max_parents", 65)
+    assert goldi.goldi_tune_get("top_max_parents") == top

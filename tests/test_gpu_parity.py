@@ -190,6 +190,21 @@ def test_schedule_independence(prm, rows, parents, l12_rows, l12_parents):
             goldi.goldi_tune_set(k, v)
 
 
+@pytest.mark.parametrize("top", [0, 1, 2, 7, 64])
+def test_top_of_tree_in_one_launch(prm, top):
+    # The levels from the first one of at most `top` parents up to the root run
+    # in one single-workgroup launch (0: every level its own launch); ragged
+    # levels and trees that start below the cut-over included.
+    banner("top of tree, top_max_parents %d" % top)
+    old = goldi.goldi_tune_get("top_max_parents")
+    try:
+        goldi.goldi_tune_set("top_max_parents", top)
+        for n, w in [(1, 8), (2, 3), (3, 8), (5, 8), (13, 9), (127, 8), (128, 8), (129, 8), (300, 1), (4097, 8)]:
+            check_tree_full(prm, n, w, seed=11 * n + w + top)
+    finally:
+        goldi.goldi_tune_set("top_max_parents", old)
+
+
 def test_tree_wide_rows_full_size_sampled(prm):
     # Wide-row commitment tree: 2^21 rows x 256 columns, column-major (4 GiB),
     # seed 2; generated on the device; sampled rows and parents checked.
