@@ -123,6 +123,15 @@ def sparse_form(rc, mds, half_full: int = 4, partial: int = 22):
     return {"k": k, "c_end": c_end, "row": row, "col": col, "pre": pre, "pre_m": pre_m, "lag": lag}
 
 
+def cap0_constants(rc, mds):
+    """Row constants of round 0's matrix for a state whose words 8..11 are
+    zero: those words enter the S-box as C[0][8..11], so their outputs and
+    matrix terms are constants, folded into C[1]:
+      C[1][i] + sum_k M[i][8+k] C[0][8+k]^7  (mod p)."""
+    caps = [pow(rc[0][8 + k], 7, P) for k in range(4)]
+    return [(rc[1][i] + sum(mds[i][8 + k] * caps[k] for k in range(4))) % P for i in range(12)]
+
+
 def _limbs22(x: int):
     return [x & 0x3FFFFF, (x >> 22) & 0x3FFFFF, x >> 44]
 
@@ -192,10 +201,7 @@ def render(spec: dict, source: str = "synth/poseidon12.json") -> str:
     lines.append("}")
     rc_int = [[int(v) for v in row] for row in spec["rc"]]
     mds_int = [[int(v) for v in row] for row in mds]
-    # A state whose words 8..11 are zero: their round-0 S-box outputs are
-    # constants, folded with their matrix terms into row i's next constant.
-    caps = [pow(rc_int[0][8 + k], 7, P) for k in range(4)]
-    r1 = [(rc_int[1][i] + sum(mds_int[i][8 + k] * caps[k] for k in range(4))) % P for i in range(12)]
+    r1 = cap0_constants(rc_int, mds_int)
     lines.append("// GOLDI_CAP0_RC1[i]: C[1][i] + sum_k M[i][8+k] C[0][8+k]^7 (mod p), split as above.")
     lines.append("#define GOLDI_CAP0_RC1_INIT {%s}" % ", ".join("{0x%08xull, 0x%08xull}" % (v & 0xFFFFFFFF, v >> 32)
                                                               for v in r1))

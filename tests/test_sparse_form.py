@@ -139,3 +139,17 @@ def test_limb_split_roundtrip():
     for x in [0, 1, P - 1, 2**63, 0x123456789ABCDEF0 % P]:
         l = gc._limbs22(x)
         assert all(v < 2**22 for v in l) and l[0] + (l[1] << 22) + (l[2] << 44) == x
+
+
+def test_zero_capacity_round0_constants():
+    # Round 0 of a state whose words 8..11 are zero, as the kernels take it
+    # (S-boxes of words 0..7 only, the matrix over those words, CAP0_RC1 as
+    # the row constants), equals the textbook round 0 followed by C[1].
+    rc, mds = load_constants()
+    r1 = gc.cap0_constants(rc, mds)
+    for st in _states(6, seed=43):
+        x = [int(v) for v in st[:8]] + [0] * 4
+        y = [sbox((x[i] + rc[0][i]) % P) for i in range(W)]
+        want = [(sum(mds[i][j] * y[j] for j in range(W)) + rc[1][i]) % P for i in range(W)]
+        got = [(sum(mds[i][j] * y[j] for j in range(8)) + r1[i]) % P for i in range(W)]
+        assert got == want
