@@ -76,6 +76,24 @@ def test_quad_cutovers_in_batches(prm, knobs):
             assert (to_host(o).reshape(-1, 4) == w_).all()
 
 
+@pytest.mark.parametrize("forced", [True, False])
+def test_single_chunk_batches(prm, knobs, forced):
+    # Every tree of the batch has rows of at most 8 words, so the batched leaf
+    # kernel takes its single-absorption form; forced onto one lane per state
+    # for small trees, and by size with the default cut-overs.
+    banner("build_many single-chunk rows, forced=%s" % forced)
+    if forced:
+        for k in ("quad_max_rows", "quad_max_parents", "lane12_max_rows", "lane12_max_parents"):
+            knobs(k, 0)
+        batch = small_batch(14, 12, 0, 11, widths=(1, 5, 8))
+    else:
+        batch = small_batch(15, 6, 13, 16, widths=(2, 8))
+    trees = [(to_dev(lv), n, w) for n, w, lv in batch]
+    outs = goldi.goldi_merkle_build_many(trees)
+    for (n, w, lv), o in zip(batch, outs):
+        assert (to_host(o).reshape(-1, 4) == oracle.merkle_build(prm, lv, n, w)).all(), (n, w)
+
+
 def test_graph_replays_with_eager_work_between(prm, knobs):
     # A captured graph is replayed several times, with other (eager) work and
     # synchronisations in between; every replay must equal the eager result.
