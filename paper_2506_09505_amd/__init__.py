@@ -246,8 +246,13 @@ def goldi_profile_read(kernel: str):
     return ms.value, cnt.value
 
 
+TUNE_KEYS = ("quad_max_rows", "quad_max_parents", "lane12_max_rows", "lane12_max_parents", "top_max_parents",
+             "batch_mode", "graph")
+
+
 def goldi_tune_set(key: str, value: int) -> None:
-    """Set a schedule knob ("quad_max_rows", "quad_max_parents"); results never change."""
+    """Set a schedule knob (one of TUNE_KEYS, documented in include/goldi.h);
+    every setting computes the same bytes, only speed changes."""
     _check(lib().goldi_tune_set(key.encode(), value), "goldi_tune_set")
 
 

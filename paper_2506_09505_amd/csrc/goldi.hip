@@ -382,9 +382,9 @@ constexpr size_t kGraphCacheMax = 16;
 hipStream_t g_capture_stream[kMaxDevices] = {};
 
 int launch_many_graph(int dev, const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
-    std::vector<uint64_t> key = {(uint64_t)dev,          (uint64_t)(uintptr_t)status, quad_max_rows(),
-                                 quad_max_parents(),   l12_max_rows(),                l12_max_parents(),
-                                 g_batch_mode.load()};
+    std::vector<uint64_t> key = {(uint64_t)dev,        (uint64_t)(uintptr_t)status, quad_max_rows(),
+                                 quad_max_parents(), l12_max_rows(),                l12_max_parents(),
+                                 top_max_parents(),  g_batch_mode.load()};
     for (size_t t = 0; t < n_trees; t++) {
         key.push_back((uint64_t)(uintptr_t)trees[t].leaves);
         key.push_back(trees[t].n_rows);

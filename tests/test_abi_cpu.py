@@ -60,6 +60,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         goldi.lib()
 
 
+def test_every_documented_knob_reads_back():
+    for k in goldi.TUNE_KEYS:
+        v = goldi.goldi_tune_get(k)
+        goldi.goldi_tune_set(k, v)
+        assert goldi.goldi_tune_get(k) == v
+
+
 def test_tune_knobs_cpu():
     old = goldi.goldi_tune_get("quad_max_rows")
     goldi.goldi_tune_set("quad_max_rows", 123)
