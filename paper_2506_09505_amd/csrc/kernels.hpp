@@ -1,6 +1,9 @@
 // Device kernels of the Merkle builder: permutation, leaf linear hash and
-// level reduce.  One state per lane throughout (Sec. 2.4's state of 12
-// words in 24 VGPRs); see poseidon.hpp for the permutation itself.
+// level reduce, each in three layouts of one permutation (poseidon.hpp: one
+// state per lane, the state's 12 words in 24 VGPRs; poseidon_quad.hpp: four
+// lanes per state; poseidon_lane12.hpp: one word per lane), the tree top in
+// one single-workgroup launch, and the batched variants that cover up to 64
+// trees per launch.
 #pragma once
 #include <hip/hip_runtime.h>
 
