@@ -199,7 +199,7 @@ def main() -> int:
     torch.cuda.synchronize()
     goldi.goldi_profile_enable(False)
     breakdown = {k: goldi.goldi_profile_read(k) for k in ("leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level",
-                                                          "level_quad", "level_lane12")}
+                                                          "level_quad", "level_lane12", "top_lane12")}
     if int(status.item()) != 0:
         print("device status %d: non-canonical input" % int(status.item()), file=sys.stderr)
         return 1
