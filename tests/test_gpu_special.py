@@ -98,3 +98,36 @@ def test_leaf_layouts_closed_form(name, layout):
         s = [(a + int(b)) % P for a, b in zip(s[:4], rows[r, 8:])] + s[4:]
         s = closed_form(name, s)
         assert [int(v) for v in got[r]] == s[:4], (layout, r)
+
+
+@pytest.mark.parametrize("name", ["identity", "shift", "const"])
+def test_single_chunk_rows_and_nodes_closed_form(name):
+    # Rows of at most 8 words (one absorption of a zero-capacity state, only
+    # the digest kept) and the tree nodes above them, one lane per state:
+    # the permutations with the shortened first round and the digest-only
+    # last matrix, against the closed form.
+    L = load(name)
+    for k in (b"quad_max_rows", b"quad_max_parents", b"lane12_max_rows", b"lane12_max_parents",
+              b"top_max_parents"):
+        assert L.goldi_tune_set(k, 0) == 0
+    L.goldi_merkle_build.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_void_p]
+    L.goldi_merkle_num_nodes.restype = ctypes.c_size_t
+    L.goldi_merkle_num_nodes.argtypes = [ctypes.c_size_t]
+    n, w = 37, 8
+    lv = goldilocks_words(42, 0, 0, n * w)
+    out = to_dev(np.zeros(L.goldi_merkle_num_nodes(n) * 4, dtype=np.uint64))
+    assert L.goldi_merkle_build(to_dev(lv).data_ptr(), n, w, out.data_ptr()) == 0
+    got = to_host(out).reshape(-1, 4)
+    rows = lv.reshape(w, n).T
+    level = [closed_form(name, [int(v) for v in rows[r]] + [0] * 4)[:4] for r in range(n)]
+    want = list(level)
+    while len(level) > 1:
+        nxt = []
+        for i in range(0, len(level), 2):
+            if i + 1 < len(level):
+                nxt.append(closed_form(name, level[i] + level[i + 1] + [0] * 4)[:4])
+            else:
+                nxt.append(level[i])
+        want += nxt
+        level = nxt
+    assert [[int(v) for v in g] for g in got] == want
