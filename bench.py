@@ -110,9 +110,18 @@ def cpu_baseline(n_rows: int, n_cols: int, seed: int):
     nodes = oracle.merkle_build(prm, lv, n, n_cols, threads=threads)
     dt = time.perf_counter() - t0
     perms = perms_per_build(n, n_cols)
+    # The same oracle on one thread, over a smaller tree of the same shape.
+    n1 = 1 << 15
+    lv1 = leaves_colmajor(n1, n_cols, seed=seed)
+    t1 = time.perf_counter()
+    oracle.merkle_build(prm, lv1, n1, n_cols, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": perms / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
             "sample": "one 2^18-leaf x %d-word tree (seed %d, %d permutations) built by the oracle "
-                      "in %.2f s" % (n_cols, seed, perms, dt)}, (lv, nodes, n)
+                      "in %.2f s" % (n_cols, seed, perms, dt),
+            "single_thread_value": perms_per_build(n1, n_cols) / dt1,
+            "single_thread_sample": "one 2^15-leaf x %d-word tree on one thread in %.2f s" % (n_cols, dt1)}, \
+        (lv, nodes, n)
 
 
 def main() -> int:
@@ -131,7 +140,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
 
