@@ -131,6 +131,11 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
  *                      sequence into a hipGraph, cached per batch description
  *                      (pointers, sizes, status word, knobs; 16 most recent),
  *                      and replay it; 0 (default) = launch directly.
+ * goldi_tune_get also reads "partial_form", fixed when the library is
+ * compiled: how the one-state-per-lane permutation evaluates the partial
+ * rounds (2 = blocks of three rounds as one product with 32-bit entries,
+ * 1 = the sparse form of Sec. 2.4 / Alg. 1, 0 = the dense matrix every
+ * round); goldi_tune_set rejects it with GOLDI_EINVAL.
  * Returns GOLDI_EINVAL for an unknown key or a null pointer. */
 int goldi_tune_set(const char *key, size_t value);
 int goldi_tune_get(const char *key, size_t *value);

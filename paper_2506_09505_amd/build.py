@@ -38,9 +38,10 @@ def _jobs(gen_constants):
     for inc in gen_constants.write_specials():
         name = os.path.basename(inc)[len("special_"):-len(".inc")]
         yield special_lib(name), sources(), ['-DGOLDI_CONSTANTS_INC="%s"' % os.path.basename(inc)]
-    # Test-only: the seeded instance with dense partial rounds everywhere, so
-    # that form stays checked against the oracle.
-    yield special_lib("dense"), sources(), ["-DGOLDI_PARTIAL_SPARSE=0"]
+    # Test-only: the seeded instance with the partial rounds in the sparse
+    # form and in the dense form, so that both stay checked against the oracle.
+    yield special_lib("sparse"), sources(), ["-DGOLDI_PARTIAL_FORM=1"]
+    yield special_lib("dense"), sources(), ["-DGOLDI_PARTIAL_FORM=0"]
 
 
 def build(verbose: bool = False) -> str:

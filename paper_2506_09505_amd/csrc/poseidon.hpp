@@ -14,12 +14,15 @@
 // and one partial-round body keep the code small enough for the instruction
 // cache, which a fully unrolled permutation (~17k instructions) would not.
 //
-// Partial rounds: by default in the sparse form of Alg. 1 (MDSPartial: one
-// pre-matrix, then per round a matrix that is the identity apart from a full
-// first row and first column, with full-size 64-bit entries), which measured
-// faster on MI355X than the dense product with 6-bit entries (2 multiply-adds
-// per term).  GOLDI_PARTIAL_SPARSE=0 selects the dense form, as does an
-// instance whose lower-right 11 x 11 block of M is singular (no sparse form).
+// Partial rounds: by default three at a time, as one product with the
+// 32-bit integer matrix (M P)^3 (P zeroes word 0) plus the block's S-box
+// outputs times integer columns, the first partial round riding on the last
+// opening round's matrix.  A v_mad_u64_u32 costs the same for a 26-bit entry
+// as for a 6-bit one, so a block of three costs about 1.3 dense rounds.  The
+// sparse form of Alg. 1 (MDSPartial: one pre-matrix, then per round the
+// identity apart from a full first row and column with 64-bit entries) and
+// the dense form (the textbook matrix every round) stay selectable with
+// GOLDI_PARTIAL_FORM=1 and 0; they measured slower on MI355X.
 #pragma once
 #include "field.hpp"
 #ifdef GOLDI_CONSTANTS_INC
@@ -169,10 +172,19 @@ __device__ __forceinline__ void full_round(u64 s[WIDTH], int r) {
 // group (plus precomputed scalars times the group's earlier S-box outputs),
 // so each word takes all the group's column terms in one reduction, from the
 // constant limbs times s, s 2^22 and s 2^44 (mod p).
-#ifndef GOLDI_PARTIAL_SPARSE
-#define GOLDI_PARTIAL_SPARSE 1
+// GOLDI_PARTIAL_FORM: 2 = blocks of partial rounds (below; the default),
+// 1 = the sparse form, 0 = dense.  An instance without the chosen form falls
+// back to the next one down.
+#ifndef GOLDI_PARTIAL_FORM
+#define GOLDI_PARTIAL_FORM 2
 #endif
-#if GOLDI_PARTIAL_SPARSE && GOLDI_SPARSE_OK
+#if GOLDI_PARTIAL_FORM >= 2 && GOLDI_BLOCK_OK
+#define GOLDI_USE_BLOCKS 1
+#define GOLDI_USE_SPARSE 0
+#else
+#define GOLDI_USE_BLOCKS 0
+#endif
+#if !GOLDI_USE_BLOCKS && GOLDI_PARTIAL_FORM >= 1 && GOLDI_SPARSE_OK
 #define GOLDI_USE_SPARSE 1
 __constant__ u32 SP_K[PARTIAL + 1][3] = GOLDI_SP_K_INIT;
 __constant__ u32 SP_CEND[WIDTH - 1][2] = GOLDI_SP_CEND_INIT;
@@ -180,7 +192,7 @@ __constant__ u32 SP_ROW[PARTIAL][WIDTH - 1][3] = GOLDI_SP_ROW_INIT;
 __constant__ u32 SP_COL22[PARTIAL][WIDTH - 1][3] = GOLDI_SP_COL22_INIT;
 __constant__ u32 SP_LAG[PARTIAL][3][3] = GOLDI_SP_LAG_INIT;
 __constant__ u32 SP_PRE_M[WIDTH - 1][WIDTH][3] = GOLDI_SP_PRE_M_INIT;
-#else
+#elif !GOLDI_USE_BLOCKS
 #define GOLDI_USE_SPARSE 0
 #endif
 
@@ -301,6 +313,156 @@ __device__ __forceinline__ void sparse_group(u64 s[WIDTH], int j) {
 }
 #endif
 
+#if GOLDI_USE_BLOCKS
+// ---------------------------------------------------------------------------
+// Partial rounds GOLDI_BLK at a time.  With P the projection that zeroes word
+// 0 and c0 the first column of M, a partial round maps a state b that holds
+// its round constant to M P b + c0 S(b_0) + C[r + 1]; m rounds map it to
+//   A_m b + sum_(j<m) f_m[j] S_j + K_m,   A_m = (M P)^m, f_m[j] = A_(m-1-j) c0,
+// with S_j the S-box output of round j of the block.  A_m and f_m do not
+// depend on the block and, with the instance's small entries, are integers
+// below 2^26 (the generator checks a bound on every row), so:
+//   * the S-box inputs of rounds 1 .. GOLDI_BLK-1 of the block are row 0 of
+//     A_m b plus the earlier S-box terms: one dot product each;
+//   * the state after the block is one dense product with 32-bit entries,
+//     whose dozen-odd 32 x 32-bit products per accumulator stay below 2^58.
+// Each product is one v_mad_u64_u32 like the full rounds' 6-bit entries, so a
+// block of three rounds costs about as much as 1.3 dense rounds.  Entries
+// above 64 are not inline constants; they go into scalar registers (a VOP3
+// instruction reads one), and each row's first term, the newest S-box output
+// times c0[i] (an inline constant), takes the row's constant as its addend
+// straight from the scalar registers it was loaded into.
+__constant__ u64 BLK_K[GOLDI_BLK_N][GOLDI_BLK - 1 + WIDTH][2] = GOLDI_BLK_K_INIT;
+__constant__ u64 BLK_LEAD_K[WIDTH][2] = GOLDI_BLK_LEAD_K_INIT;
+
+template <unsigned C>
+__device__ __forceinline__ u64 mad_coef(u32 x, u64 acc) {
+    if constexpr (C <= 64) {
+        return mad_small<C>(x, acc);
+    } else {
+        u64 r;
+        asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(r) : "v"(x), "s"(C), "v"(acc) : "vcc");
+        return r;
+    }
+}
+
+// Terms j = J .. 11 of row I of A_M (column 0 is zero).
+template <int M, int I, int J = 1>
+__device__ __forceinline__ void blk_words(const u64 s[WIDTH], u64 &a_lo, u64 &a_hi) {
+    constexpr unsigned C = GOLDI_BLK_A[M - 1][I][J];
+    a_lo = mad_coef<C>(lo32(s[J]), a_lo);
+    a_hi = mad_coef<C>(hi32(s[J]), a_hi);
+    if constexpr (J + 1 < WIDTH) blk_words<M, I, J + 1>(s, a_lo, a_hi);
+}
+
+// Terms of the S-box outputs x[J] .. x[0] of row I of f_M.
+template <int M, int I, int J>
+__device__ __forceinline__ void blk_sterms(const u64 x[GOLDI_BLK], u64 &a_lo, u64 &a_hi) {
+    if constexpr (J >= 0) {
+        constexpr unsigned C = GOLDI_BLK_F[M - 1][I][J];
+        a_lo = mad_coef<C>(lo32(x[J]), a_lo);
+        a_hi = mad_coef<C>(hi32(x[J]), a_hi);
+        blk_sterms<M, I, J - 1>(x, a_lo, a_hi);
+    }
+}
+
+// Word I of the state M rounds into the block, as a weak word; k = its
+// constant K_M[I] split as RC_SPLIT.
+template <int M, int I>
+__device__ __forceinline__ u64 blk_row(const u64 s[WIDTH], const u64 x[GOLDI_BLK], const u64 (&k)[2]) {
+    static_assert(GOLDI_BLK_F[M - 1][I][M - 1] == GOLDI_MDS[I][0], "newest S-box term is c0");
+    u64 a_lo = mad_small_sacc<GOLDI_MDS[I][0]>(lo32(x[M - 1]), k[0]);
+    u64 a_hi = mad_small_sacc<GOLDI_MDS[I][0]>(hi32(x[M - 1]), k[1]);
+    blk_sterms<M, I, M - 2>(x, a_lo, a_hi);
+    blk_words<M, I>(s, a_lo, a_hi);
+    return reduce_split(a_lo, a_hi);
+}
+
+// S-box outputs of rounds 1 .. GOLDI_BLK-1 of the block.
+template <int M>
+__device__ __forceinline__ void blk_chain(const u64 s[WIDTH], u64 x[GOLDI_BLK], const u64 (*kc)[2]) {
+    if constexpr (M < GOLDI_BLK) {
+        const u64 k[2] = {kc[M - 1][0], kc[M - 1][1]};
+        x[M] = sbox(blk_row<M, 0>(s, x, k));
+        blk_chain<M + 1>(s, x, kc);
+    }
+}
+
+template <int I, int I1>
+__device__ __forceinline__ void blk_rows_range(const u64 s[WIDTH], const u64 x[GOLDI_BLK], u64 out[WIDTH],
+                                               const u64 (&k)[WIDTH][2]) {
+    out[I] = blk_row<GOLDI_BLK, I>(s, x, k[I]);
+    if constexpr (I + 1 < I1) blk_rows_range<I + 1, I1>(s, x, out, k);
+}
+
+// Rows I0 .. 11 of the state after the block, a group of rows' constants
+// read together.
+template <int I0>
+__device__ __forceinline__ void blk_rows(const u64 s[WIDTH], const u64 x[GOLDI_BLK], u64 out[WIDTH],
+                                         const u64 (*kc)[2]) {
+    constexpr int I1 = I0 + GOLDI_RC_GROUP < WIDTH ? I0 + GOLDI_RC_GROUP : WIDTH;
+    u64 k[WIDTH][2];
+#pragma unroll
+    for (int i = I0; i < I1; i++) {
+        k[i][0] = kc[i][0];
+        k[i][1] = kc[i][1];
+    }
+    blk_rows_range<I0, I1>(s, x, out, k);
+    if constexpr (I1 < WIDTH) blk_rows<I1>(s, x, out, kc);
+}
+
+// The first partial round rides on the last opening full round's matrix:
+// from that round's S-box outputs y, the partial round's S-box input is
+// u = row 0 of M y + C[HALF_FULL][0], and the state after it is
+// (M P M) y + c0 S(u) + M P C[HALF_FULL] + C[HALF_FULL + 1].
+template <int I, int J = 0>
+__device__ __forceinline__ void lead_words(const u64 y[WIDTH], u64 &a_lo, u64 &a_hi) {
+    constexpr unsigned C = GOLDI_BLK_LEAD_B[I][J];
+    a_lo = mad_coef<C>(lo32(y[J]), a_lo);
+    a_hi = mad_coef<C>(hi32(y[J]), a_hi);
+    if constexpr (J + 1 < WIDTH) lead_words<I, J + 1>(y, a_lo, a_hi);
+}
+
+template <int I, int I1>
+__device__ __forceinline__ void lead_rows_range(const u64 y[WIDTH], u64 x, u64 out[WIDTH], const u64 (&k)[WIDTH][2]) {
+    u64 a_lo = mad_small_sacc<GOLDI_MDS[I][0]>(lo32(x), k[I][0]);
+    u64 a_hi = mad_small_sacc<GOLDI_MDS[I][0]>(hi32(x), k[I][1]);
+    lead_words<I>(y, a_lo, a_hi);
+    out[I] = reduce_split(a_lo, a_hi);
+    if constexpr (I + 1 < I1) lead_rows_range<I + 1, I1>(y, x, out, k);
+}
+
+template <int I0>
+__device__ __forceinline__ void lead_rows(const u64 y[WIDTH], u64 x, u64 out[WIDTH]) {
+    constexpr int I1 = I0 + GOLDI_RC_GROUP < WIDTH ? I0 + GOLDI_RC_GROUP : WIDTH;
+    u64 k[WIDTH][2];
+#pragma unroll
+    for (int i = I0; i < I1; i++) {
+        k[i][0] = BLK_LEAD_K[i][0];
+        k[i][1] = BLK_LEAD_K[i][1];
+    }
+    lead_rows_range<I0, I1>(y, x, out, k);
+    if constexpr (I1 < WIDTH) lead_rows<I1>(y, x, out);
+}
+
+__device__ __forceinline__ void lead_matrix(const u64 y[WIDTH], u64 out[WIDTH]) {
+    u64 u[WIDTH];
+    mds_rows<0, 1>(y, u, RC_SPLIT[HALF_FULL]);
+    lead_rows<0>(y, sbox(u[0]), out);
+}
+
+__device__ __forceinline__ void partial_block(u64 s[WIDTH], int b) {
+    const u64 (*kc)[2] = BLK_K[b];
+    u64 x[GOLDI_BLK];
+    x[0] = sbox(s[0]);
+    blk_chain<1>(s, x, kc);
+    u64 out[WIDTH];
+    blk_rows<0>(s, x, out, kc + GOLDI_BLK - 1);
+#pragma unroll
+    for (int i = 0; i < WIDTH; i++) s[i] = out[i];
+}
+#endif
+
 __device__ __forceinline__ void partial_round(u64 s[WIDTH], int r) {
     s[0] = sbox(s[0]);
     mds_add_rc(s, r + 1);
@@ -332,13 +494,21 @@ __device__ __forceinline__ void permute(u64 s[WIDTH], bool cap0 = false, bool di
 #if GOLDI_USE_SPARSE
         else if (r + 1 == HALF_FULL)
             pre_matrix(s, out);
+#elif GOLDI_USE_BLOCKS
+        else if (r + 1 == HALF_FULL)
+            lead_matrix(s, out);
 #endif
         else
             mds_row_group<0>(s, out, RC_SPLIT[r + 1]);
 #pragma unroll
         for (int i = 0; i < WIDTH; i++) s[i] = out[i];
     }
-#if GOLDI_USE_SPARSE
+#if GOLDI_USE_BLOCKS
+#pragma nounroll
+    for (int b = 0; b < GOLDI_BLK_N; b++) partial_block(s, b);
+#pragma unroll
+    for (int r = GOLDI_BLK_FIRST_TAIL; r < HALF_FULL + PARTIAL; r++) partial_round(s, r);
+#elif GOLDI_USE_SPARSE
     // Pairs: larger groups measured slower (their constants no longer fit the
     // scalar registers of one group).
 #pragma nounroll

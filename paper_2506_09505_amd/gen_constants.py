@@ -17,8 +17,12 @@ tables the kernels compile against:
   from C and M by ``sparse_form`` below.  Full-width entries that enter dot
   products are split into three 22-bit limbs (a 32 x 22-bit product is below
   2^54, so a dozen of them add up in 64 bits without carries).
+* the constants of the partial rounds taken three at a time (``block_form``):
+  the integer matrices (M P)^m and their columns, the first partial round
+  folded into the last opening round's matrix, and per-block constants.
 
-Apart from ``sparse_form`` the script only reformats.
+Apart from ``sparse_form``, ``block_form`` and ``cap0_constants`` the script
+only reformats.
 """
 
 from __future__ import annotations
@@ -123,6 +127,70 @@ def sparse_form(rc, mds, half_full: int = 4, partial: int = 22):
     return {"k": k, "c_end": c_end, "row": row, "col": col, "pre": pre, "pre_m": pre_m, "lag": lag}
 
 
+BLOCK = 3            # partial rounds per block
+BLOCK_ROW_SUM = 1 << 31  # bound on a block row's coefficients (see block_form)
+
+
+def block_form(rc, mds, k: int = BLOCK, half_full: int = 4, partial: int = 22):
+    """Constants of the partial rounds taken k at a time.
+
+    A partial round on a state b that already holds its round constant is
+    b' = M P b + c0 S(b_0) + C[r+1], with P the projection that zeroes word 0
+    and c0 the first column of M.  Over m consecutive rounds from b:
+      b_(m) = A_m b + sum_(j<m) f_m[j] S_j + K_m,
+    where A_m = (M P)^m, f_m[j] = A_(m-1-j) c0, S_j is the S-box output of
+    round j of the block (its input is word 0 of b_(j)), and
+    K_m = sum_(j=1..m) A_(m-j) C[r+j].  A_m and f_m are the same for every
+    block and, for small matrix entries and small m, are integers far below
+    2^32, so a block costs one dense product with 32-bit entries instead of
+    m products.
+
+    The first partial round is not in a block: it joins the matrix of the
+    last opening full round (lead_b, lead_k below).
+
+    Returns None unless every entry of A_m (m <= k), f_m and lead_b is below
+    2^32 and every row's coefficients sum to at most BLOCK_ROW_SUM (so that a
+    row's products of 32-bit limbs add up in 64 bits), else a dict:
+      a[m]    = A_m (12 x 12 integers, column 0 zero for m >= 1), m = 0..k;
+      f[m]    = f_m as f[m][i][j] (12 x m integers), m = 1..k;
+      lead_b  = M P M (12 x 12 integers);
+      lead_k  = M P C[half_full] + C[half_full + 1] (mod p);
+      starts  = first round of each block (half_full + 1, half_full + 1 + k, ...);
+      tail    = the partial rounds after the last block (taken one by one);
+      kc[b]   = block b's constants: K_1[0] .. K_(k-1)[0], then K_k[0..11]."""
+    w12 = len(mds)
+    mp = [[0 if j == 0 else mds[i][j] for j in range(w12)] for i in range(w12)]
+    c0 = [mds[i][0] for i in range(w12)]
+    a = [_identity(w12)]
+    for _ in range(k):
+        a.append([[sum(mp[i][t] * a[-1][t][j] for t in range(w12)) for j in range(w12)] for i in range(w12)])
+    f = [None]
+    for m in range(1, k + 1):
+        f.append([[sum(a[m - 1 - j][i][t] * c0[t] for t in range(w12)) for j in range(m)] for i in range(w12)])
+    # The first partial round joins the last opening full round's matrix:
+    # from the S-box outputs y of that round, the state after the partial
+    # round is (M P M) y + c0 S(row 0 of M y + C[h][0]) + M P C[h] + C[h+1]
+    # (h = half_full).
+    lead_b = [[sum(mp[i][t] * mds[t][j] for t in range(w12)) for j in range(w12)] for i in range(w12)]
+    rows = [a[m][i][1:] + f[m][i] for m in range(1, k + 1) for i in range(w12)]
+    rows += [lead_b[i] + [c0[i]] for i in range(w12)]
+    if any(max(r) >= 1 << 32 or sum(r) > BLOCK_ROW_SUM for r in rows):
+        return None
+    h = half_full
+    lead_k = [(x + y) % P for x, y in zip(_mv(mp, rc[h]), rc[h + 1])]
+    n_blocks = (partial - 1) // k
+    starts = [h + 1 + k * b for b in range(n_blocks)]
+    tail = list(range(h + 1 + k * n_blocks, h + partial))
+    kc = []
+    for r in starts:
+        ks = []
+        for m in range(1, k + 1):
+            km = [sum(_mv(a[m - j], rc[r + j])[i] for j in range(1, m + 1)) % P for i in range(w12)]
+            ks.append(km)
+        kc.append([ks[m - 1][0] for m in range(1, k)] + ks[k - 1])
+    return {"a": a, "f": f, "starts": starts, "tail": tail, "kc": kc, "k": k, "lead_b": lead_b, "lead_k": lead_k}
+
+
 def cap0_constants(rc, mds):
     """Row constants of round 0's matrix for a state whose words 8..11 are
     zero: those words enter the S-box as C[0][8..11], so their outputs and
@@ -178,6 +246,39 @@ def render_sparse(rc, mds) -> list:
     return lines
 
 
+def render_blocks(rc, mds) -> list:
+    bf = block_form(rc, mds)
+    lines = ["// Partial rounds in blocks (see gen_constants.block_form)."]
+    if bf is None:
+        lines.append("#define GOLDI_BLOCK_OK 0  // block coefficients too large for 32-bit limbs")
+        return lines
+    k = bf["k"]
+    lines.append("#define GOLDI_BLOCK_OK 1")
+    lines.append("#define GOLDI_BLK %d  // partial rounds per block" % k)
+    lines.append("#define GOLDI_BLK_N %d  // blocks; the partial rounds after them go one by one" % len(bf["starts"]))
+    lines.append("#define GOLDI_BLK_FIRST_TAIL %d  // first partial round after the blocks" %
+                 (bf["tail"][0] if bf["tail"] else bf["starts"][-1] + k))
+    assert bf["starts"][0] == 5, "the lead round is partial round 4"
+    lines.append("// GOLDI_BLK_A[m-1] = (M P)^m, m = 1..%d (P zeroes word 0): exact integers." % k)
+    lines.append("static constexpr unsigned GOLDI_BLK_A[%d][12][12] = %s;" % (
+        k, "{" + ", ".join("{" + ", ".join("{" + ", ".join("%du" % v for v in row) + "}" for row in bf["a"][m]) + "}"
+                           for m in range(1, k + 1)) + "}"))
+    lines.append("// GOLDI_BLK_F[m-1][i][j] = ((M P)^(m-1-j) c0)_i for j < m (c0 = column 0 of M), else 0.")
+    lines.append("static constexpr unsigned GOLDI_BLK_F[%d][12][%d] = %s;" % (
+        k, k, "{" + ", ".join("{" + ", ".join("{" + ", ".join("%du" % (bf["f"][m][i][j] if j < m else 0)
+                                                                 for j in range(k)) + "}" for i in range(12)) + "}"
+                              for m in range(1, k + 1)) + "}"))
+    lines.append("// GOLDI_BLK_LEAD_B = M P M: the last opening round's matrix with the first partial round.")
+    lines.append("static constexpr unsigned GOLDI_BLK_LEAD_B[12][12] = %s;" % (
+        "{" + ", ".join("{" + ", ".join("%du" % v for v in row) + "}" for row in bf["lead_b"]) + "}"))
+    lines.append("// GOLDI_BLK_LEAD_K = M P C[4] + C[5] (mod p), split as RC_SPLIT.")
+    lines.append(_c_array("GOLDI_BLK_LEAD_K", "u64", [12, 2], [h for v in bf["lead_k"] for h in (v & 0xFFFFFFFF, v >> 32)]))
+    lines.append("// GOLDI_BLK_K[b]: block b's constants K_1[0] .. K_%d[0], K_%d[0..11], split as RC_SPLIT." % (k - 1, k))
+    cells = [h for blk in bf["kc"] for v in blk for h in (v & 0xFFFFFFFF, v >> 32)]
+    lines.append(_c_array("GOLDI_BLK_K", "u64", [len(bf["kc"]), k - 1 + 12, 2], cells))
+    return lines
+
+
 def render(spec: dict, source: str = "synth/poseidon12.json") -> str:
     rc = [[int(v) for v in row] for row in spec["rc"]] + [[0] * 12]
     mds = spec["mds"]
@@ -206,6 +307,7 @@ def render(spec: dict, source: str = "synth/poseidon12.json") -> str:
     lines.append("#define GOLDI_CAP0_RC1_INIT {%s}" % ", ".join("{0x%08xull, 0x%08xull}" % (v & 0xFFFFFFFF, v >> 32)
                                                               for v in r1))
     lines.extend(render_sparse(rc_int, mds_int))
+    lines.extend(render_blocks(rc_int, mds_int))
     return "\n".join(lines) + "\n"
 
 

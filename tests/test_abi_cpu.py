@@ -67,6 +67,20 @@ def test_every_documented_knob_reads_back():
         assert goldi.goldi_tune_get(k) == v
 
 
+@pytest.mark.parametrize("name,form", [(None, 2), ("sparse", 1), ("dense", 0)])
+def test_partial_form_of_each_build(name, form):
+    # The default library takes the partial rounds in blocks; the test-only
+    # builds keep the sparse and the dense forms.  The key is read-only.
+    from paper_2506_09505_amd import build
+    L = ctypes.CDLL(goldi.LIB_PATH if name is None else build.special_lib(name))
+    L.goldi_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]
+    L.goldi_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    v = ctypes.c_size_t(99)
+    assert L.goldi_tune_get(b"partial_form", ctypes.byref(v)) == 0
+    assert v.value == form
+    assert L.goldi_tune_set(b"partial_form", form) == goldi.GOLDI_EINVAL
+
+
 def test_tune_knobs_cpu():
     old = goldi.goldi_tune_get("quad_max_rows")
     goldi.goldi_tune_set("quad_max_rows", 123)

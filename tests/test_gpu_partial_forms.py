@@ -1,8 +1,9 @@
 """The default library evaluates the partial rounds of the one-state-per-lane
-kernels in sparse form; the dense form (the textbook matrix in every round)
-stays built as a test library on the seeded instance.  Both must give the
-oracle's results bit for bit: permutations (random and edge states) and a
-ragged tree built with one lane per state at every level."""
+kernels in blocks of three; the sparse form (Sec. 2.4, Alg. 1) and the dense
+form (the textbook matrix in every round) stay built as test libraries on the
+seeded instance.  Each must give the oracle's results bit for bit:
+permutations (random and edge states) and a ragged tree built with one lane
+per state at every level."""
 
 import ctypes
 import os
@@ -18,10 +19,13 @@ from .gpu_util import banner, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 
-def load_dense():
+FORMS = ["sparse", "dense"]
+
+
+def load_form(form):
     import torch  # noqa: F401  (bind to torch's HIP runtime first)
     from paper_2506_09505_amd import build
-    path = build.special_lib("dense")
+    path = build.special_lib(form)
     assert os.path.exists(path), "build the libraries first"
     L = ctypes.CDLL(path)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
@@ -30,6 +34,10 @@ def load_dense():
     L.goldi_merkle_num_nodes.restype = sz
     L.goldi_merkle_num_nodes.argtypes = [sz]
     L.goldi_tune_set.argtypes = [ctypes.c_char_p, sz]
+    L.goldi_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(sz)]
+    v = sz(99)
+    assert L.goldi_tune_get(b"partial_form", ctypes.byref(v)) == 0
+    assert v.value == {"sparse": 1, "dense": 0}[form]
     return L
 
 
@@ -38,9 +46,10 @@ def prm():
     return oracle.spec_params()
 
 
-def test_dense_form_permute(prm):
-    banner("dense form: permute 4096 random + edge states")
-    L = load_dense()
+@pytest.mark.parametrize("form", FORMS)
+def test_form_permute(prm, form):
+    banner("%s form: permute 4096 random + edge states" % form)
+    L = load_form(form)
     x = np.concatenate([uniform_states(4096, seed=50), edge_states()])
     d = to_dev(x)
     assert L.goldi_poseidon_permute(d.data_ptr(), x.shape[0]) == 0
@@ -48,9 +57,10 @@ def test_dense_form_permute(prm):
     assert (got == oracle.permute(prm, x)).all()
 
 
-def test_dense_form_tree(prm):
-    banner("dense form: tree 3001 x 9, one lane per state")
-    L = load_dense()
+@pytest.mark.parametrize("form", FORMS)
+def test_form_tree(prm, form):
+    banner("%s form: tree 3001 x 9, one lane per state" % form)
+    L = load_form(form)
     for k in (b"quad_max_rows", b"quad_max_parents", b"lane12_max_rows", b"lane12_max_parents"):
         assert L.goldi_tune_set(k, 0) == 0
     n, w = 3001, 9
