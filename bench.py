@@ -34,9 +34,9 @@ METRIC = "Poseidon-12 perms/s + 2^22-leaf Merkle build ms; batched vs plain, bit
 #   S-boxes: (8 full rounds x 12 + 22 partial rounds x 1) x 4 field products
 #            x 4 limb products                                  = 1,888
 #   matrix:  30 rounds x 144 entries x 2 limb products (entries < 2^32) = 8,640
-# The kernels reach the same permutation with less: sparse partial rounds,
-# round-0 S-boxes of constant capacity words skipped, only the digest rows of
-# the last matrix.  The work is still counted as the textbook's, as a flop
+# The kernels reach the same permutation with less: partial rounds three at a
+# time as one product with small integer entries, round-0 S-boxes of constant
+# capacity words skipped, only the digest rows of the last matrix.  The work is still counted as the textbook's, as a flop
 # rate counts the schoolbook operations of a faster algorithm.
 MULADDS_PER_PERM = 1888 + 8640
 OP_TEXT = ("32x32->64-bit multiply-add (v_mad_u64_u32), %d per permutation of the textbook dense form; "
