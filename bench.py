@@ -10,8 +10,10 @@ the timed region; the timed region holds exactly ``--steps`` builds.
 Printed: one JSON line with the headline (permutations per second over the
 whole build), the build time, a roofline entry for the dominant kernel
 (integer multiply-adds per second against the chip's 32-bit multiply-add
-peak, from HIP events recorded on the launch stream during the timed region)
-and the CPU oracle's rate on a bounded sample of the same workload.
+peak, from HIP events recorded on the launch stream during the timed region;
+with the committed HBM counters, bytes per launch and the fraction of HBM
+peak), the spread of single builds (an untimed pass with one event pair per
+build), and the CPU oracle's rate on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -44,6 +46,8 @@ OP_TEXT = ("32x32->64-bit multiply-add (v_mad_u64_u32), %d per permutation of th
 # gfx950 peak of that operation: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
 # v_mad_u64_u32 per lane per cycle (measured full rate on MI355X).
 PEAK_MULADD_PER_S = 256 * 4 * 16 * 2.4e9
+# MI355X HBM3E peak, bytes/s (to show how far below it the path runs).
+PEAK_HBM_BYTES_PER_S = 8.0e12
 
 WORKLOADS = {
     # name: (n_rows, n_cols, seed, description)
@@ -96,6 +100,25 @@ def traffic_from_profiles(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def step_stats(samples_ms):
+    """Mean, standard deviation and minimum of per-build times (ms)."""
+    n = len(samples_ms)
+    mean = sum(samples_ms) / n
+    var = sum((x - mean) ** 2 for x in samples_ms) / max(1, n - 1)
+    return {"builds": n, "mean_ms": round(mean, 4), "std_ms": round(var ** 0.5, 4), "min_ms": round(min(samples_ms), 4)}
+
+
 def cpu_baseline(n_rows: int, n_cols: int, seed: int):
     """The oracle (plain textbook C, all host threads) on a bounded sample:
     a 2^18-leaf tree of the same leaf shape (524,287 permutations)."""
@@ -117,6 +140,7 @@ def cpu_baseline(n_rows: int, n_cols: int, seed: int):
     oracle.merkle_build(prm, lv1, n1, n_cols, threads=1)
     dt1 = time.perf_counter() - t1
     return {"value": perms / dt, "unit": "perms/s", "cores": threads, "kind": "oracle",
+            "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(),
             "sample": "one 2^18-leaf x %d-word tree (seed %d, %d permutations) built by the oracle "
                       "in %.2f s" % (n_cols, seed, perms, dt),
             "single_thread_value": perms_per_build(n1, n_cols) / dt1,
@@ -200,6 +224,15 @@ def main() -> int:
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     kernels = {"leaf_hash": goldi.goldi_profile_read(leaf_kind)}
 
+    # Untimed pass for the spread: one event pair around each build.
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per_build = step_stats([a.elapsed_time(b) for a, b in evs])
+
     # Untimed breakdown pass: every kernel bracketed (adds a few us per launch).
     goldi.goldi_profile_select(None)
     goldi.goldi_profile_enable(True)
@@ -223,6 +256,10 @@ def main() -> int:
                 "op": OP_TEXT,
                 "kernel_ms": round(leaf_ms_avg, 4),
                 "traffic": traffic_from_profiles("k_" + leaf_kind, args.workload)}
+    if roofline["traffic"]:
+        hbm = roofline["traffic"] / (leaf_ms_avg * 1e-3)
+        roofline["hbm_gb_per_s"] = round(hbm / 1e9, 1)
+        roofline["hbm_frac"] = round(hbm / PEAK_HBM_BYTES_PER_S, 4)
 
     out = {
         "metric": METRIC,
@@ -240,6 +277,7 @@ def main() -> int:
         "config": {"workload": desc, "n_rows": n_rows, "n_cols": n_cols, "seed": seed,
                    "perms_per_step": perms, "build_ms": round(ms_per_step, 4),
                    "wall_ms_per_step": round(wall_ms / args.steps, 4),
+                   "build_ms_each": per_build,
                    "breakdown_ms_per_build": {k: round(v[0] / 3, 4) for k, v in breakdown.items()},
                    "breakdown_launches_per_build": {k: v[1] // 3 for k, v in breakdown.items()}},
         "roofline": roofline,
