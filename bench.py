@@ -86,10 +86,10 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def profile_record(name: str, kernel: str, workload: str):
+    """A committed rocprofv3 counter summary (profiles/<name>) for one kernel
+    and workload, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             rec = json.load(f).get("%s/%s" % (kernel, workload))
@@ -97,7 +97,13 @@ def traffic_from_profiles(kernel: str, workload: str):
         return None
     if not rec or rec.get("source_digest") != source_digest():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled), or None."""
+    rec = profile_record("traffic.json", kernel, workload)
+    return rec.get("hbm_bytes_per_launch") if rec else None
 
 
 def host_cpu_model() -> str:
@@ -256,6 +262,15 @@ def main() -> int:
                 "op": OP_TEXT,
                 "kernel_ms": round(leaf_ms_avg, 4),
                 "traffic": traffic_from_profiles("k_" + leaf_kind, args.workload)}
+    valu = profile_record("valu.json", "k_" + leaf_kind, args.workload)
+    if valu and leaf_kind == "leaf_hash":
+        # One state per lane: a wave runs 64 permutations.  The issue limit is
+        # one wave64 VALU instruction per SIMD every 4 cycles at 2.4 GHz.
+        per_perm = valu["valu_instructions_per_permutation"]
+        rate = leaf_perms / 64 * per_perm / (leaf_ms_avg * 1e-3)
+        roofline["valu_issue"] = {"instructions_per_permutation": per_perm,
+                                  "frac_of_issue_limit": round(rate / (256 * 4 * 2.4e9 / 4), 4),
+                                  "source": "profiles/valu.json (SQ_INSTS_VALU / SQ_WAVES) with the live kernel time"}
     if roofline["traffic"]:
         hbm = roofline["traffic"] / (leaf_ms_avg * 1e-3)
         roofline["hbm_gb_per_s"] = round(hbm / 1e9, 1)
