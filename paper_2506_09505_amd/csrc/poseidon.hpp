@@ -320,8 +320,8 @@ __device__ __forceinline__ void sparse_group(u64 s[WIDTH], int j) {
 // its round constant to M P b + c0 S(b_0) + C[r + 1]; m rounds map it to
 //   A_m b + sum_(j<m) f_m[j] S_j + K_m,   A_m = (M P)^m, f_m[j] = A_(m-1-j) c0,
 // with S_j the S-box output of round j of the block.  A_m and f_m do not
-// depend on the block and, with the instance's small entries, are integers
-// below 2^26 (the generator checks a bound on every row), so:
+// depend on the block and, with the instance's 6-bit entries, are integers
+// whose rows sum to below 2^26 (the generator checks a bound on every row), so:
 //   * the S-box inputs of rounds 1 .. GOLDI_BLK-1 of the block are row 0 of
 //     A_m b plus the earlier S-box terms: one dot product each;
 //   * the state after the block is one dense product with 32-bit entries,
