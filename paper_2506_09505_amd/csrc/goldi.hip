@@ -123,12 +123,19 @@ int timed_launch(const char *name, hipStream_t st, F launch) {
         return GOLDI_OK;
     }
     ProfRecord r{name, nullptr, nullptr};
-    GOLDI_HIP(hipEventCreate(&r.start));
-    GOLDI_HIP(hipEventCreate(&r.stop));
-    GOLDI_HIP(hipEventRecord(r.start, st));
+    // On any failure the events are released before the error is returned.
+    auto drop = [&r](const char *what, hipError_t e) {
+        if (r.start) (void)hipEventDestroy(r.start);
+        if (r.stop) (void)hipEventDestroy(r.stop);
+        return fail(GOLDI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipEventCreate(&r.start);
+    if (e != hipSuccess) return drop("hipEventCreate", e);
+    if ((e = hipEventCreate(&r.stop)) != hipSuccess) return drop("hipEventCreate", e);
+    if ((e = hipEventRecord(r.start, st)) != hipSuccess) return drop("hipEventRecord", e);
     launch();
-    GOLDI_HIP(hipGetLastError());
-    GOLDI_HIP(hipEventRecord(r.stop, st));
+    if ((e = hipGetLastError()) != hipSuccess) return drop("kernel launch", e);
+    if ((e = hipEventRecord(r.stop, st)) != hipSuccess) return drop("hipEventRecord", e);
     std::lock_guard<std::mutex> lock(g_prof_mu);
     g_prof.push_back(r);
     return GOLDI_OK;
