@@ -31,20 +31,26 @@ if ROOT not in sys.path:
 
 METRIC = "Poseidon-12 perms/s + 2^22-leaf Merkle build ms; batched vs plain, bit-exact"
 
-# Algorithmic work of one permutation, in 32x32->64-bit multiply-adds, for
-# the textbook definition evaluated on 32-bit limbs (schoolbook products):
-#   S-boxes: (8 full rounds x 12 + 22 partial rounds x 1) x 4 field products
-#            x 4 limb products                                  = 1,888
-#   matrix:  30 rounds x 144 entries x 2 limb products (entries < 2^32) = 8,640
-# The kernels reach the same permutation with less: partial rounds three at a
-# time as one product with small integer entries, round-0 S-boxes of constant
-# capacity words skipped, only the digest rows of the last matrix.  The work is still counted as the textbook's, as a flop
-# rate counts the schoolbook operations of a faster algorithm.
-MULADDS_PER_PERM = 1888 + 8640
-OP_TEXT = ("32x32->64-bit multiply-add (v_mad_u64_u32), %d per permutation of the textbook dense form; "
-           "the kernels reach the same result with fewer" % MULADDS_PER_PERM)
+# Algorithmic work of one permutation, in 32x32->64-bit multiply-adds on
+# 32-bit limbs, for the optimised form of the permutation that Alg. 1 (Sec.
+# 2.4) describes -- sparse partial rounds after one pre-matrix:
+#   full-width field products: 118 S-boxes x 4 products + the pre-matrix's
+#     121 + 22 partial rounds x (12 + 11)                 = 1,099, x 4 = 4,396
+#   small-entry matrix terms: 8 full rounds x 144 entries  = 1,152, x 2 = 2,304
+# total 6,700 per permutation (reductions, carries and additions are not
+# counted, the way a flop count leaves out index arithmetic).  This is the
+# work of the method, not of the textbook form with the dense matrix in every
+# round (DENSE_MULADDS_PER_PERM below, reported only as a labelled secondary
+# figure).
+MULADDS_PER_PERM = 1099 * 4 + 1152 * 2
+OP_TEXT = ("32x32->64-bit multiply-add (v_mad_u64_u32), %d per permutation: the optimised form of Alg. 1 "
+           "(1,099 full-width products x 4 limb products + 1,152 small matrix terms x 2)" % MULADDS_PER_PERM)
+# The textbook form (dense 12x12 matrix in all 30 rounds):
+#   S-boxes 118 x 4 x 4 = 1,888; matrix 30 x 144 x 2 = 8,640.
+DENSE_MULADDS_PER_PERM = 1888 + 8640
 # gfx950 peak of that operation: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
-# v_mad_u64_u32 per lane per cycle (measured full rate on MI355X).
+# v_mad_u64_u32 per lane per cycle (one wave64 instruction per SIMD every 4
+# cycles).  The measured rate of the instruction is in profiles/rates.json.
 PEAK_MULADD_PER_S = 256 * 4 * 16 * 2.4e9
 # MI355X HBM3E peak, bytes/s (to show how far below it the path runs).
 PEAK_HBM_BYTES_PER_S = 8.0e12
@@ -64,6 +70,8 @@ WORKLOADS = {
     "batch64": (None, None, 3, "batched: 64 trees, rows floor(2^U) with U uniform on [10, 20], widths uniform "
                                "in {8,16,32,64,128}, uniform Goldilocks words (seed 3); autotuned batched "
                                "schedule vs 64 plain single-tree launches"),
+    "rates": (None, None, 0, "per-opcode issue rates of the gfx950 vector ALU for the field layer's integer "
+                             "instructions (inline assembly, 8 waves per SIMD; one wave alone for latency)"),
 }
 
 
@@ -161,6 +169,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="tree22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="tree22: skip the batched-vs-plain and 2^24-state permutation records")
     ap.add_argument("--requests", type=int, default=1000, help="serve: measured requests (after 100 warm-up)")
     ap.add_argument("--serve-input", default="host", choices=("host", "device"),
                     help="serve: leaves in pinned host memory (copied in by the server) or already in HBM")
@@ -188,7 +198,6 @@ def main() -> int:
         return 0
 
     import paper_2506_09505_amd as goldi
-    from synth import fill
 
     if args.workload == "batch64":
         return bench_batch(args)
@@ -196,7 +205,66 @@ def main() -> int:
         return bench_serve(args)
     if args.workload == "functions":
         return bench_functions(args)
+    if args.workload == "rates":
+        return bench_rates(args)
+    return bench_tree(args, goldi, np, torch)
 
+
+KINDS = ("leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level", "level_quad", "level_lane12", "top_lane12")
+
+
+def schedule(goldi, n_rows: int, n_cols: int):
+    """Permutations and launches per kernel kind of one build, following the
+    library's schedule knobs (an unpaired last node is moved, not hashed)."""
+    t = {k: goldi.goldi_tune_get(k) for k in ("lane12_max_rows", "quad_max_rows", "lane12_max_parents",
+                                               "quad_max_parents", "top_max_parents")}
+    perms = dict.fromkeys(KINDS, 0)
+    launches = dict.fromkeys(KINDS, 0)
+    leaf = ("leaf_hash_lane12" if n_rows <= t["lane12_max_rows"] else
+            "leaf_hash_quad" if n_rows <= t["quad_max_rows"] else "leaf_hash")
+    perms[leaf] += n_rows * ((n_cols + 7) // 8)
+    launches[leaf] += 1
+    n, top = n_rows, False
+    while n > 1:
+        par = (n + 1) // 2
+        if not top and par <= t["top_max_parents"]:
+            top = True
+            launches["top_lane12"] += 1
+        kind = ("top_lane12" if top else "level_lane12" if par <= t["lane12_max_parents"] else
+                "level_quad" if par <= t["quad_max_parents"] else "level")
+        perms[kind] += n // 2
+        if not top:
+            launches[kind] += 1
+        n = par
+    return perms, launches
+
+
+def measured_mad_rate():
+    """Throughput of v_mad_u64_u32 as a fraction of the full rate, from the
+    committed rate-probe summary, or None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "rates.json")) as f:
+            return json.load(f)["rates"]["v_mad_u64_u32"]["throughput_frac_of_full_rate"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def golden_record(key: str):
+    """The oracle's per-level digests and root for a workload, as recorded by
+    tests/golden/make_golden.py (which calls only the oracle), or None."""
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "fullsize.json")) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def root_words(nodes_dev, torch, np):
+    return [str(int(v)) for v in nodes_dev.view(-1, 4)[-1].view(torch.int64).cpu().numpy().view(np.uint64)]
+
+
+def bench_tree(args, goldi, np, torch) -> int:
+    from synth import fill
     n_rows, n_cols, seed, desc = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -205,77 +273,127 @@ def main() -> int:
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     perms = perms_per_build(n_rows, n_cols)
+    sched_perms, sched_launches = schedule(goldi, n_rows, n_cols)
+    assert sum(sched_perms.values()) == perms
+
+    def build():
+        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
 
     for _ in range(args.warmup):
-        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
+        build()
     torch.cuda.synchronize()
 
+    # Untimed breakdown pass: every kernel bracketed (adds a few us per
+    # launch); it names the dominant kernel kind, the one with the most time
+    # per build.
+    goldi.goldi_profile_select(None)
+    goldi.goldi_profile_enable(True)
+    for _ in range(3):
+        build()
+    torch.cuda.synchronize()
+    goldi.goldi_profile_enable(False)
+    breakdown = {k: goldi.goldi_profile_read(k) for k in KINDS}
+    dominant = max(KINDS, key=lambda k: breakdown[k][0])
+
     # Timed region: exactly `steps` builds.  The library brackets each launch
-    # of the dominant kernel (the leaf hash) with HIP events on the launch
-    # stream; the other kernels run unbracketed.
-    leaf_kind = ("leaf_hash_lane12" if n_rows <= goldi.goldi_tune_get("lane12_max_rows") else
-                 "leaf_hash_quad" if n_rows <= goldi.goldi_tune_get("quad_max_rows") else "leaf_hash")
-    goldi.goldi_profile_select(leaf_kind)
+    # of the dominant kernel kind with HIP events on the launch stream; the
+    # other kernels run unbracketed.
+    goldi.goldi_profile_select(dominant)
     goldi.goldi_profile_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
+        build()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
     goldi.goldi_profile_enable(False)
+    goldi.goldi_profile_select(None)
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    kernels = {"leaf_hash": goldi.goldi_profile_read(leaf_kind)}
+    dom_ms, dom_launches = goldi.goldi_profile_read(dominant)
 
     # Untimed pass for the spread: one event pair around each build.
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     for a, b in evs:
         a.record(stream)
-        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
+        build()
         b.record(stream)
     torch.cuda.synchronize()
     per_build = step_stats([a.elapsed_time(b) for a, b in evs])
-
-    # Untimed breakdown pass: every kernel bracketed (adds a few us per launch).
-    goldi.goldi_profile_select(None)
-    goldi.goldi_profile_enable(True)
-    for _ in range(3):
-        goldi.goldi_merkle_build_async(leaves, n_rows, n_cols, nodes, status, stream)
-    torch.cuda.synchronize()
-    goldi.goldi_profile_enable(False)
-    breakdown = {k: goldi.goldi_profile_read(k) for k in ("leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level",
-                                                          "level_quad", "level_lane12", "top_lane12")}
     if int(status.item()) != 0:
         print("device status %d: non-canonical input" % int(status.item()), file=sys.stderr)
         return 1
 
-    # Dominant kernel: the leaf hash (n_rows * ceil(n_cols/8) permutations per launch).
-    leaf_ms_avg = kernels["leaf_hash"][0] / max(1, kernels["leaf_hash"][1])
-    leaf_perms = n_rows * ((n_cols + 7) // 8)
-    achieved = leaf_perms * MULADDS_PER_PERM / (leaf_ms_avg * 1e-3)
-    roofline = {"bound": "alu", "kernel": "k_" + leaf_kind,
+    # Roofline of the dominant kind: its algorithmic multiply-adds per launch
+    # over its average launch duration, both from the timed region.
+    mad_frac = measured_mad_rate()
+
+    def fracs(work_per_s):
+        f = {"frac": round(work_per_s / PEAK_MULADD_PER_S, 4)}
+        if mad_frac:
+            f["frac_of_measured_mad_rate"] = round(work_per_s / (PEAK_MULADD_PER_S * mad_frac), 4)
+        return f
+
+    runs = max(1, args.steps)
+    dom_launch_ms = dom_ms / max(1, dom_launches)
+    dom_perms_per_launch = sched_perms[dominant] / max(1, sched_launches[dominant])
+    achieved = dom_perms_per_launch * MULADDS_PER_PERM / (dom_launch_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": "k_" + dominant,
                 "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_MULADD_PER_S / 1e12, 3),
-                "unit": "Tops/s", "frac": round(achieved / PEAK_MULADD_PER_S, 4),
-                "op": OP_TEXT,
-                "kernel_ms": round(leaf_ms_avg, 4),
-                "traffic": traffic_from_profiles("k_" + leaf_kind, args.workload)}
-    valu = profile_record("valu.json", "k_" + leaf_kind, args.workload)
-    if valu and leaf_kind == "leaf_hash":
-        # One state per lane: a wave runs 64 permutations.  The issue limit is
-        # one wave64 VALU instruction per SIMD every 4 cycles at 2.4 GHz.
+                "unit": "Tops/s"}
+    roofline.update(fracs(achieved))
+    roofline.update({
+        "op": OP_TEXT,
+        "kernel_ms_per_launch": round(dom_launch_ms, 4),
+        "launches_per_build": round(dom_launches / runs, 2),
+        "perms_per_launch": dom_perms_per_launch,
+        "traffic": traffic_from_profiles("k_" + dominant, args.workload)})
+    # Every kernel kind and the whole build on the same scale (the kinds from
+    # the untimed breakdown pass, the build from the timed region).
+    per_kind = {}
+    for k in KINDS:
+        ms_k = breakdown[k][0] / 3
+        if breakdown[k][1] and sched_perms[k]:
+            rate = sched_perms[k] * MULADDS_PER_PERM / (ms_k * 1e-3)
+            per_kind["k_" + k] = dict(ms_per_build=round(ms_k, 4), perms_per_build=sched_perms[k],
+                                      launches_per_build=breakdown[k][1] // 3, **fracs(rate))
+    whole = perms * MULADDS_PER_PERM / (ms_per_step * 1e-3)
+    roofline["per_kernel"] = per_kind
+    roofline["whole_build"] = dict(achieved=round(whole / 1e12, 3), **fracs(whole))
+    roofline["dense_equivalent"] = {
+        "note": "the same times counted with the textbook form's %d multiply-adds per permutation (dense matrix "
+                "in every round), which the kernels do not execute" % DENSE_MULADDS_PER_PERM,
+        "kernel_frac": round(dom_perms_per_launch * DENSE_MULADDS_PER_PERM / (dom_launch_ms * 1e-3)
+                             / PEAK_MULADD_PER_S, 4),
+        "whole_build_frac": round(perms * DENSE_MULADDS_PER_PERM / (ms_per_step * 1e-3) / PEAK_MULADD_PER_S, 4)}
+    if mad_frac:
+        roofline["measured_mad_rate"] = {"frac_of_full_rate": mad_frac, "source": "profiles/rates.json"}
+    valu = profile_record("valu.json", "k_" + dominant, args.workload)
+    if valu and dominant in ("leaf_hash", "level"):
+        # One state per lane: a wave runs 64 permutations.  Issued VALU
+        # instructions per SIMD per cycle at 2.4 GHz (0.25 = one wave64
+        # instruction every 4 cycles; some 32-bit instructions issue faster).
         per_perm = valu["valu_instructions_per_permutation"]
-        rate = leaf_perms / 64 * per_perm / (leaf_ms_avg * 1e-3)
+        rate = dom_perms_per_launch / 64 * per_perm / (dom_launch_ms * 1e-3)
         roofline["valu_issue"] = {"instructions_per_permutation": per_perm,
-                                  "frac_of_issue_limit": round(rate / (256 * 4 * 2.4e9 / 4), 4),
+                                  "instructions_per_simd_per_cycle": round(rate / (256 * 4 * 2.4e9), 4),
                                   "source": "profiles/valu.json (SQ_INSTS_VALU / SQ_WAVES) with the live kernel time"}
     if roofline["traffic"]:
-        hbm = roofline["traffic"] / (leaf_ms_avg * 1e-3)
+        hbm = roofline["traffic"] / (dom_launch_ms * 1e-3)
         roofline["hbm_gb_per_s"] = round(hbm / 1e9, 1)
         roofline["hbm_frac"] = round(hbm / PEAK_HBM_BYTES_PER_S, 4)
 
+    config = {"workload": desc, "n_rows": n_rows, "n_cols": n_cols, "seed": seed,
+              "perms_per_step": perms, "build_ms": round(ms_per_step, 4),
+              "wall_ms_per_step": round(wall_ms / args.steps, 4),
+              "build_ms_each": per_build,
+              "breakdown_ms_per_build": {k: round(v[0] / 3, 4) for k, v in breakdown.items()},
+              "breakdown_launches_per_build": {k: v[1] // 3 for k, v in breakdown.items()}}
+    gold = golden_record(args.workload)
+    if gold:
+        config["root_equals_oracle"] = root_words(nodes, torch, np) == gold["root"]
     out = {
         "metric": METRIC,
         "value": perms / (ms_per_step * 1e-3),
@@ -289,14 +407,14 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": desc, "n_rows": n_rows, "n_cols": n_cols, "seed": seed,
-                   "perms_per_step": perms, "build_ms": round(ms_per_step, 4),
-                   "wall_ms_per_step": round(wall_ms / args.steps, 4),
-                   "build_ms_each": per_build,
-                   "breakdown_ms_per_build": {k: round(v[0] / 3, 4) for k, v in breakdown.items()},
-                   "breakdown_launches_per_build": {k: v[1] // 3 for k, v in breakdown.items()}},
+        "config": config,
         "roofline": roofline,
     }
+    del leaves, nodes
+    torch.cuda.empty_cache()
+    if args.workload == "tree22" and not args.no_extras:
+        out["batched"] = batched_vs_plain(args, goldi, np, torch)
+        out["permute"] = permute_rate(args, goldi, torch)
     if not args.no_cpu_baseline:
         base, (lv, want, n_s) = cpu_baseline(n_rows, n_cols, seed)
         # The same sample on the GPU must agree word for word.
@@ -304,6 +422,101 @@ def main() -> int:
         base["bit_exact_vs_gpu"] = bool((got.view(torch.int64).cpu().numpy().view(np.uint64).reshape(-1, 4)
                                          == want).all())
         out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def batched_vs_plain(args, goldi, np, torch):
+    """The batched workload (64 uneven trees, seed 3) built by one
+    goldi_merkle_build_many call under the default schedule, against the same
+    64 trees built one after another with the plain single-tree kernels; both
+    outputs compared word for word, and the 64 roots with the oracle's."""
+    from synth import fill
+    from synth.inputs import tree_shapes
+    dev = torch.device("cuda:0")
+    rows, ws = tree_shapes(3, 64, 10, 20, (8, 16, 32, 64, 128))
+    trees = [(fill.leaves_colmajor_dev(int(n), int(w), seed=3, stream=k, device=dev), int(n), int(w))
+             for k, (n, w) in enumerate(zip(rows, ws))]
+    outs = [torch.empty(goldi.goldi_merkle_num_nodes(n) * 4, dtype=torch.uint64, device=dev) for _, n, _ in trees]
+    plain = [torch.empty_like(o) for o in outs]
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    perms = sum(perms_per_build(n, w) for _, n, w in trees)
+    steps = max(3, args.steps // 4)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    def run_plain():
+        for (lv, n, w), o in zip(trees, plain):
+            goldi.goldi_merkle_build_async(lv, n, w, o, status, stream)
+
+    def run_many():
+        goldi.goldi_merkle_build_many_async(trees, outs, status, stream)
+
+    plain_ms = timed(run_plain)
+    many_ms = timed(run_many)
+    exact = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(outs, plain))
+    rec = {"workload": WORKLOADS["batch64"][3].replace("autotuned batched schedule", "default batched schedule"),
+           "trees": 64, "perms": perms, "plain_64_builds_ms": round(plain_ms, 4), "batched_ms": round(many_ms, 4),
+           "speedup_vs_plain": round(plain_ms / many_ms, 3), "batched_perms_per_s": perms / (many_ms * 1e-3),
+           "trees_per_s": 64 / (many_ms * 1e-3), "bit_exact_vs_plain": bool(exact),
+           "status_ok": int(status.item()) == 0, "steps": steps}
+    gold = golden_record("batch64")
+    if gold:
+        rec["roots_equal_oracle"] = all(root_words(o, torch, np) == t["root"] for o, t in zip(outs, gold["trees"]))
+    del trees, outs, plain
+    torch.cuda.empty_cache()
+    return rec
+
+
+def permute_rate(args, goldi, torch):
+    """goldi_poseidon_permute on 2^24 uniform states (1.5 GiB), in place."""
+    from synth import fill
+    n = 1 << 24
+    dev = torch.device("cuda:0")
+    states = torch.empty(n * 12, dtype=torch.uint64, device=dev)
+    fill.fill_words(states, 8, 1)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    steps = max(3, args.steps // 4)
+    goldi.goldi_poseidon_permute_async(states, status, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        goldi.goldi_poseidon_permute_async(states, status, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    rate = n / (ms * 1e-3)
+    del states
+    torch.cuda.empty_cache()
+    return {"states": n, "ms": round(ms, 4), "perms_per_s": rate, "status_ok": int(status.item()) == 0,
+            "frac": round(rate * MULADDS_PER_PERM / PEAK_MULADD_PER_S, 4), "steps": steps}
+
+
+def bench_rates(args) -> int:
+    import torch
+
+    from paper_2506_09505_amd import fieldbench
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    rows = fieldbench.rates()
+    out = {"metric": "gfx950 VALU issue rate per opcode", "value": rows["v_mad_u64_u32"]["throughput_frac_of_full_rate"],
+           "unit": "fraction of one wave64 instruction per SIMD per 4 cycles at 2.4 GHz (v_mad_u64_u32)",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": (time.perf_counter() - t0) * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": WORKLOADS["rates"][3]}, "rates": rows}
     print(json.dumps(out), flush=True)
     return 0
 

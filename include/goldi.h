@@ -61,7 +61,11 @@ enum {
     GOLDI_EINVAL = -1,    /* bad argument (null, zero size, overflow)        */
     GOLDI_ENONCANON = -2, /* an input word was >= p                          */
     GOLDI_EDEVICE = -3,   /* a HIP call failed; see goldi_last_error()       */
-    GOLDI_ENOMEM = -4     /* a device allocation failed                      */
+    GOLDI_ENOMEM = -4,    /* a device allocation failed                      */
+    GOLDI_ECANCELED = -5, /* serving: the request was still queued when the
+                             server was destroyed                            */
+    GOLDI_ETIMEDOUT = -6  /* serving: the request's batch did not complete
+                             within the server's watchdog time               */
 };
 
 /* Poseidon-12 permutation (Sec. 2.4, Alg. 1) of n states, in place.
@@ -110,6 +114,14 @@ int goldi_merkle_build_async(const uint64_t *leaves, size_t n_rows, size_t n_col
                              uint32_t *dev_status, void *stream);
 int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
                                   void *stream);
+
+/* goldi_merkle_build_many_async with one status word per tree: tree k
+ * (in the order of `trees`) ORs its bits into dev_status[k], so a tree with
+ * a non-canonical word is reported alone and every other tree of the call
+ * is built exactly as goldi_merkle_build would build it alone.
+ * dev_status: device array of n_trees words, zeroed by the caller. */
+int goldi_merkle_build_many_status_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
+                                         void *stream);
 
 /* Schedule knobs (process-wide).  Every setting computes the same bytes;
  * only speed changes.  Keys:
@@ -166,11 +178,22 @@ int goldi_profile_read(const char *kernel, double *total_ms, size_t *count);
  * on the device with those already running.  Per request the server holds,
  * in device memory from the stream-ordered allocator, a copy of host leaves
  * (freed when the build completes) and all nodes (kept until released).
- * The root is returned to the host.  All server calls are thread-safe. */
+ * The root is returned to the host.  All server calls are thread-safe.
+ *
+ * Failure isolation: every request of a batch has its own device status word,
+ * so a request holding a word >= p fails alone (GOLDI_ENONCANON) and its
+ * batch-mates complete normally.  If a whole batch fails on the host side
+ * (an allocation or launch error), each of its requests is queued again at
+ * the head of the queue and rebuilt in a batch of its own; only a request
+ * that fails alone too is reported failed.  A watchdog marks the requests of
+ * a batch that has not completed within the watchdog time GOLDI_ETIMEDOUT
+ * and wakes their waiters; the batch's device memory is kept until the GPU
+ * work really completes (a release in the meantime is deferred until then). */
 typedef struct goldi_server goldi_server;
 
 typedef struct {
-    int status;            /* GOLDI_OK, GOLDI_ENONCANON or GOLDI_EDEVICE       */
+    int status;            /* GOLDI_OK, GOLDI_ENONCANON, GOLDI_EDEVICE,
+                              GOLDI_ETIMEDOUT or GOLDI_ECANCELED               */
     size_t n_rows, n_cols;
     uint64_t *nodes;       /* device, level-major nodes; valid until release  */
     int64_t t_submit_ns;   /* steady-clock times of submission, admission and */
@@ -206,7 +229,21 @@ int goldi_server_release(goldi_server *s, uint64_t id);
 /* Requests admitted, batches formed and the peak of admitted device bytes. */
 int goldi_server_stats(goldi_server *s, size_t *admitted, size_t *groups, size_t *peak_bytes);
 
-/* Finishes every queued request, then frees the server (unreleased nodes too). */
+/* Server settings (keys):
+ *   "watchdog_us"        time a batch may run before its requests are marked
+ *                        GOLDI_ETIMEDOUT (default 30 s; 0 disables);
+ *   "fail_next_batches"  a fault-injection hook for tests: the next `value`
+ *                        batches of two or more requests are treated as if
+ *                        their launch had failed, before anything is
+ *                        enqueued for them (so their requests take the
+ *                        rebuild-alone path).
+ * Returns GOLDI_EINVAL for an unknown key. */
+int goldi_server_set(goldi_server *s, const char *key, uint64_t value);
+
+/* Stops the server: requests still queued (not admitted) are completed with
+ * GOLDI_ECANCELED, admitted batches are waited for, then the server and all
+ * unreleased nodes are freed.  No call on `s` may run concurrently with or
+ * after it. */
 int goldi_server_destroy(goldi_server *s);
 
 /* The admission rule, exposed so it can be checked without a GPU: with

@@ -41,6 +41,44 @@ int goldi_fb_eval(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, s
  * the kernel time.  seed: 2 device words; out: `threads` device words. */
 int goldi_fb_throughput(int op, const uint64_t *seed, uint64_t *out, size_t threads, int iters, float *ms);
 
+/* Per-opcode issue rates of the vector ALU (the isolated add/sub/multiply
+ * IPC measurements of Sec. 4.3, asked of gfx950): the integer instructions the
+ * field layer is built from, each written as inline assembly so that exactly
+ * that instruction runs, and three 1:1 mixes. */
+enum {
+    GOLDI_RATE_MAD_U64_U32 = 0,  /* 32x32 + 64 -> 64, carry-out to SGPRs      */
+    GOLDI_RATE_MUL_LO_U32,
+    GOLDI_RATE_MUL_HI_U32,
+    GOLDI_RATE_ADD_CO_U32,       /* add with carry-out to SGPRs               */
+    GOLDI_RATE_ADDC_CO_U32,      /* add with carry-in and carry-out            */
+    GOLDI_RATE_ADD_U32,          /* add without carry                          */
+    GOLDI_RATE_SUB_U32,
+    GOLDI_RATE_XOR_B32,
+    GOLDI_RATE_MOV_B32,
+    GOLDI_RATE_LSHRREV_B32,
+    GOLDI_RATE_LSHLREV_B64,
+    GOLDI_RATE_LSHL_ADD_U64,
+    GOLDI_RATE_ADD3_U32,
+    GOLDI_RATE_MAD_U32_U24,
+    GOLDI_RATE_CNDMASK_VCC,      /* v_cndmask_b32, VOP2 form reading VCC       */
+    GOLDI_RATE_CNDMASK_SGPR,     /* v_cndmask_b32_e64 with an SGPR-pair mask   */
+    GOLDI_RATE_ALIGNBIT_B32,
+    GOLDI_RATE_BFE_U32,
+    GOLDI_RATE_DOT4_U32_U8,
+    GOLDI_RATE_MIX_MAD_ADD,      /* v_mad_u64_u32 and v_add_u32, alternating   */
+    GOLDI_RATE_MIX_ADDCO_ADD,    /* v_add_co_u32 and v_add_u32, alternating    */
+    GOLDI_RATE_MIX_MAD_MOV,      /* v_mad_u64_u32 and v_mov_b32, alternating   */
+    GOLDI_RATE_COUNT
+};
+
+/* Runs `waves` single-wave workgroups (64 lanes each); every lane issues
+ * iters * 16 * chains instructions of `op` in `chains` (1 or 8) independent
+ * dependent chains, after one warm-up launch, on the null stream.  *ms (host)
+ * receives the kernel time.  out: device buffer of waves * 64 words (written
+ * with meaningless values).  waves in 1..2^20.  Returns 0, -1 for bad
+ * arguments, -3 for a HIP error. */
+int goldi_rate_probe(int op, int chains, size_t waves, int iters, uint32_t *out, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgoldi.so")
 
 GOLDI_OK, GOLDI_EINVAL, GOLDI_ENONCANON, GOLDI_EDEVICE, GOLDI_ENOMEM = 0, -1, -2, -3, -4
+GOLDI_ECANCELED, GOLDI_ETIMEDOUT = -5, -6
 P = 0xFFFFFFFF00000001
 WIDTH, RATE, DIGEST = 12, 8, 4
 
@@ -27,7 +28,8 @@ EXPORTS = ("goldi_poseidon_permute", "goldi_poseidon_permute_async", "goldi_merk
            "goldi_last_error", "goldi_profile_enable", "goldi_profile_read",
            "goldi_tune_set", "goldi_tune_get", "goldi_server_create", "goldi_server_submit",
            "goldi_server_wait", "goldi_server_release", "goldi_server_stats", "goldi_server_destroy",
-           "goldi_admission_plan", "goldi_server_read_nodes", "goldi_profile_select")
+           "goldi_admission_plan", "goldi_server_read_nodes", "goldi_profile_select",
+           "goldi_merkle_build_many_status_async", "goldi_server_set")
 
 
 class GoldiError(RuntimeError):
@@ -73,6 +75,7 @@ def lib():
         L.goldi_merkle_build_async.argtypes = [vp, sz, sz, vp, vp, vp]
         L.goldi_merkle_build_many.argtypes = [ctypes.POINTER(_Tree), sz]
         L.goldi_merkle_build_many_async.argtypes = [ctypes.POINTER(_Tree), sz, vp, vp]
+        L.goldi_merkle_build_many_status_async.argtypes = [ctypes.POINTER(_Tree), sz, vp, vp]
         L.goldi_strerror.argtypes = [ci]
         L.goldi_strerror.restype = ctypes.c_char_p
         L.goldi_last_error.restype = ctypes.c_char_p
@@ -87,6 +90,7 @@ def lib():
         L.goldi_server_release.argtypes = [vp, ctypes.c_uint64]
         L.goldi_server_stats.argtypes = [vp, psz, psz, psz]
         L.goldi_server_destroy.argtypes = [vp]
+        L.goldi_server_set.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64]
         L.goldi_server_read_nodes.argtypes = [vp, ctypes.c_uint64, vp, sz]
         L.goldi_admission_plan.argtypes = [psz, sz, sz, sz, sz, psz]
         L.goldi_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -115,13 +119,40 @@ def _torch():
     return torch
 
 
-def _dev_u64(t, what: str):
+def _dev_u64(t, what: str, min_words: int = 0, device=None):
+    """Checks that ``t`` is a contiguous uint64 device tensor holding at least
+    ``min_words`` words (on ``device`` if given); the C side can only check the
+    allocation a pointer lies in, and torch's caching allocator hands out
+    pieces of larger blocks."""
     torch = _torch()
     if not isinstance(t, torch.Tensor) or t.dtype != torch.uint64 or not t.is_cuda:
         raise TypeError("%s must be a torch.uint64 tensor on a ROCm device" % what)
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % what)
+    if t.numel() < min_words:
+        raise ValueError("%s holds %d words, %d needed" % (what, t.numel(), min_words))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (what, t.device, device))
     return t
+
+
+def _dev_status(t, words: int, device):
+    """A contiguous int32/uint32 device tensor of at least ``words`` status words."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype not in (torch.int32, torch.uint32) or not t.is_cuda:
+        raise TypeError("dev_status must be an int32 tensor on a ROCm device")
+    if not t.is_contiguous() or t.numel() < words:
+        raise ValueError("dev_status must be contiguous with at least %d words" % words)
+    if t.device != device:
+        raise ValueError("dev_status is on %s, expected %s" % (t.device, device))
+    return t
+
+
+def _positive(n: int, what: str) -> int:
+    n = int(n)
+    if n < 1:
+        raise ValueError("%s must be >= 1" % what)
+    return n
 
 
 def _stream_ptr(stream):
@@ -147,6 +178,9 @@ def goldi_poseidon_permute(states):
 
 def goldi_poseidon_permute_async(states, dev_status, stream=None):
     _dev_u64(states, "states")
+    if states.numel() % WIDTH:
+        raise ValueError("states must hold a multiple of 12 words")
+    _dev_status(dev_status, 1, states.device)
     with _torch().cuda.device(states.device):
         _check(lib().goldi_poseidon_permute_async(states.data_ptr(), states.numel() // WIDTH,
                                                   dev_status.data_ptr(), _stream_ptr(stream)),
@@ -161,18 +195,21 @@ def _alloc(n_words: int, like):
 
 def goldi_leaf_hash(leaves, n_rows: int, n_cols: int, digests=None):
     """Digests ``[n_rows, 4]`` of the rows of the column-major ``leaves``."""
-    _dev_u64(leaves, "leaves")
+    n_rows, n_cols = _positive(n_rows, "n_rows"), _positive(n_cols, "n_cols")
+    _dev_u64(leaves, "leaves", n_rows * n_cols)
     if digests is None:
         digests = _alloc(n_rows * DIGEST, leaves).view(n_rows, DIGEST)
-    _dev_u64(digests, "digests")
+    _dev_u64(digests, "digests", n_rows * DIGEST, leaves.device)
     with _torch().cuda.device(leaves.device):
         _check(lib().goldi_leaf_hash(leaves.data_ptr(), n_rows, n_cols, digests.data_ptr()), "goldi_leaf_hash")
     return digests
 
 
 def goldi_leaf_hash_async(leaves, n_rows, n_cols, digests, dev_status, stream=None):
-    _dev_u64(leaves, "leaves")
-    _dev_u64(digests, "digests")
+    n_rows, n_cols = _positive(n_rows, "n_rows"), _positive(n_cols, "n_cols")
+    _dev_u64(leaves, "leaves", n_rows * n_cols)
+    _dev_u64(digests, "digests", n_rows * DIGEST, leaves.device)
+    _dev_status(dev_status, 1, leaves.device)
     with _torch().cuda.device(leaves.device):
         _check(lib().goldi_leaf_hash_async(leaves.data_ptr(), n_rows, n_cols, digests.data_ptr(),
                                            dev_status.data_ptr(), _stream_ptr(stream)), "goldi_leaf_hash_async")
@@ -182,10 +219,11 @@ def goldi_leaf_hash_async(leaves, n_rows, n_cols, digests, dev_status, stream=No
 def goldi_merkle_build(leaves, n_rows: int, n_cols: int, nodes_out=None):
     """Every node (level-major, ``[num_nodes, 4]``) of the tree over the rows
     of the column-major ``leaves`` (``leaves[c*n_rows + r]``)."""
-    _dev_u64(leaves, "leaves")
+    n_rows, n_cols = _positive(n_rows, "n_rows"), _positive(n_cols, "n_cols")
+    _dev_u64(leaves, "leaves", n_rows * n_cols)
     if nodes_out is None:
         nodes_out = _alloc(goldi_merkle_num_nodes(n_rows) * DIGEST, leaves).view(-1, DIGEST)
-    _dev_u64(nodes_out, "nodes_out")
+    _dev_u64(nodes_out, "nodes_out", goldi_merkle_num_nodes(n_rows) * DIGEST, leaves.device)
     with _torch().cuda.device(leaves.device):
         _check(lib().goldi_merkle_build(leaves.data_ptr(), n_rows, n_cols, nodes_out.data_ptr()),
                "goldi_merkle_build")
@@ -193,8 +231,10 @@ def goldi_merkle_build(leaves, n_rows: int, n_cols: int, nodes_out=None):
 
 
 def goldi_merkle_build_async(leaves, n_rows, n_cols, nodes_out, dev_status, stream=None):
-    _dev_u64(leaves, "leaves")
-    _dev_u64(nodes_out, "nodes_out")
+    n_rows, n_cols = _positive(n_rows, "n_rows"), _positive(n_cols, "n_cols")
+    _dev_u64(leaves, "leaves", n_rows * n_cols)
+    _dev_u64(nodes_out, "nodes_out", goldi_merkle_num_nodes(n_rows) * DIGEST, leaves.device)
+    _dev_status(dev_status, 1, leaves.device)
     with _torch().cuda.device(leaves.device):
         _check(lib().goldi_merkle_build_async(leaves.data_ptr(), n_rows, n_cols, nodes_out.data_ptr(),
                                               dev_status.data_ptr(), _stream_ptr(stream)),
@@ -203,10 +243,14 @@ def goldi_merkle_build_async(leaves, n_rows, n_cols, nodes_out, dev_status, stre
 
 
 def _tree_array(trees):
+    if len(trees) == 0:
+        raise ValueError("need at least one tree")
+    dev = trees[0][0].device if hasattr(trees[0][0], "device") else None
     arr = (_Tree * len(trees))()
     for k, (leaves, n_rows, n_cols, out) in enumerate(trees):
-        _dev_u64(leaves, "leaves")
-        _dev_u64(out, "nodes_out")
+        n_rows, n_cols = _positive(n_rows, "n_rows"), _positive(n_cols, "n_cols")
+        _dev_u64(leaves, "leaves of tree %d" % k, n_rows * n_cols, dev)
+        _dev_u64(out, "nodes_out of tree %d" % k, goldi_merkle_num_nodes(n_rows) * DIGEST, dev)
         arr[k] = _Tree(leaves.data_ptr(), n_rows, n_cols, out.data_ptr())
     return arr
 
@@ -215,6 +259,8 @@ def goldi_merkle_build_many(trees, outputs=None):
     """``trees``: list of ``(leaves, n_rows, n_cols)``; returns the list of node tensors."""
     if outputs is None:
         outputs = [_alloc(goldi_merkle_num_nodes(n) * DIGEST, lv).view(-1, DIGEST) for lv, n, _ in trees]
+    if len(outputs) != len(trees):
+        raise ValueError("one output per tree")
     arr = _tree_array([(lv, n, w, o) for (lv, n, w), o in zip(trees, outputs)])
     with _torch().cuda.device(trees[0][0].device):
         _check(lib().goldi_merkle_build_many(arr, len(trees)), "goldi_merkle_build_many")
@@ -222,10 +268,27 @@ def goldi_merkle_build_many(trees, outputs=None):
 
 
 def goldi_merkle_build_many_async(trees, outputs, dev_status, stream=None):
+    if len(outputs) != len(trees):
+        raise ValueError("one output per tree")
     arr = _tree_array([(lv, n, w, o) for (lv, n, w), o in zip(trees, outputs)])
+    _dev_status(dev_status, 1, trees[0][0].device)
     with _torch().cuda.device(trees[0][0].device):
         _check(lib().goldi_merkle_build_many_async(arr, len(trees), dev_status.data_ptr(), _stream_ptr(stream)),
                "goldi_merkle_build_many_async")
+    return outputs
+
+
+def goldi_merkle_build_many_status_async(trees, outputs, dev_status, stream=None):
+    """Like goldi_merkle_build_many_async, with one status word per tree:
+    ``dev_status`` is a zeroed int32 device tensor of at least len(trees) words."""
+    if len(outputs) != len(trees):
+        raise ValueError("one output per tree")
+    arr = _tree_array([(lv, n, w, o) for (lv, n, w), o in zip(trees, outputs)])
+    _dev_status(dev_status, len(trees), trees[0][0].device)
+    with _torch().cuda.device(trees[0][0].device):
+        _check(lib().goldi_merkle_build_many_status_async(arr, len(trees), dev_status.data_ptr(),
+                                                          _stream_ptr(stream)),
+               "goldi_merkle_build_many_status_async")
     return outputs
 
 
@@ -300,6 +363,8 @@ class GoldiServer:
             if leaves.dtype != torch.uint64 or not leaves.is_contiguous():
                 raise TypeError("leaves must be a contiguous torch.uint64 tensor")
             if leaves.is_cuda:
+                if leaves.device.index != self._device:
+                    raise ValueError("leaves are on %s, the server on cuda:%d" % (leaves.device, self._device))
                 dev = leaves.data_ptr()
             else:
                 host = leaves.data_ptr()
@@ -333,6 +398,11 @@ class GoldiServer:
 
     def release(self, rid: int) -> None:
         _check(lib().goldi_server_release(self._h, rid), "goldi_server_release")
+
+    def set(self, key: str, value: int) -> None:
+        """Server setting: "watchdog_us" or the test hook "fail_next_batches"
+        (see goldi_server_set in include/goldi.h)."""
+        _check(lib().goldi_server_set(self._h, key.encode(), value), "goldi_server_set")
 
     def stats(self) -> dict:
         a, g, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()

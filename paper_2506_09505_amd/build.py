@@ -32,8 +32,9 @@ def _jobs(gen_constants):
     """(output, sources, extra flags) of every library; the test-only ones go
     to _special/."""
     yield LIB, sources(), []
-    # The Table-1 function library (device field operations, rates).
-    yield FB_LIB, [os.path.join(CSRC, "fieldbench.hip")], []
+    # The Table-1 function library (device field operations, per-function
+    # and per-opcode rates).
+    yield FB_LIB, [os.path.join(CSRC, "fieldbench.hip"), os.path.join(CSRC, "rates.hip")], []
     # Test-only libraries compiled against special instances with closed forms.
     for inc in gen_constants.write_specials():
         name = os.path.basename(inc)[len("special_"):-len(".inc")]

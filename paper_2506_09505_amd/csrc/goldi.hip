@@ -267,11 +267,19 @@ int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *
 
 size_t chunks_of(size_t n_cols) { return (n_cols + goldi::RATE - 1) / goldi::RATE; }
 
+// Where tree t of a many-tree call reports a non-canonical word: base + t *
+// stride (stride 0: one word shared by every tree).
+struct StatusMap {
+    uint32_t *base;
+    size_t stride;
+    uint32_t *of(size_t t) const { return base + t * stride; }
+};
+
 // Launches one step of a batch: fills block_begin from per-tree item counts
 // (lanes_per_item = 1, 4 or 16) and launches `kernel`.
-template <class K, class... Extra>
+template <class K>
 int launch_batch(const char *name, K kernel, goldi::Batch &b, const size_t *items, int lanes_per_item,
-                 hipStream_t st, Extra... extra) {
+                 hipStream_t st) {
     size_t blocks = 0;
     for (uint32_t t = 0; t < b.n_trees; t++) {
         unsigned g;
@@ -284,15 +292,15 @@ int launch_batch(const char *name, K kernel, goldi::Batch &b, const size_t *item
     b.block_begin[b.n_trees] = (uint32_t)blocks;
     if (blocks == 0) return GOLDI_OK;
     return timed_launch(name, st, [&] {
-        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(goldi::BLOCK), 0, st, b, extra...);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(goldi::BLOCK), 0, st, b);
     });
 }
 
 // All trees of `order` (indices into trees, at most MAX_BATCH), one launch
 // per step: the leaves of every tree, then level 1 of every tree that has
 // one, and so on.  Trees are ordered by per-row cost, heaviest first, so the
-// longest blocks are dispatched first.
-int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, uint32_t *status, hipStream_t st) {
+// longest blocks are dispatched first.  Tree t reports into status.of(t).
+int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, StatusMap status, hipStream_t st) {
     const uint32_t nt = (uint32_t)order.size();
     goldi::Batch b;
     memset(&b, 0, sizeof b);
@@ -301,18 +309,18 @@ int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, ui
     size_t total = 0, max_cols = 0;
     for (uint32_t k = 0; k < nt; k++) {
         const goldi_tree_t &T = trees[order[k]];
-        b.t[k] = {T.leaves, T.nodes_out, (uint32_t)T.n_rows, (uint32_t)T.n_cols};
+        b.t[k] = {T.leaves, T.nodes_out, status.of(order[k]), (uint32_t)T.n_rows, (uint32_t)T.n_cols};
         items[k] = T.n_rows;
         total += T.n_rows;
         max_cols = std::max(max_cols, T.n_cols);
     }
     int rc = total <= l12_max_rows()
-                 ? launch_batch("leaf_hash_lane12", goldi::k_leaf_hash_lane12_batch, b, items, 16, st, status)
+                 ? launch_batch("leaf_hash_lane12", goldi::k_leaf_hash_lane12_batch, b, items, 16, st)
              : total <= quad_max_rows()
-                 ? launch_batch("leaf_hash_quad", goldi::k_leaf_hash_quad_batch, b, items, 4, st, status)
+                 ? launch_batch("leaf_hash_quad", goldi::k_leaf_hash_quad_batch, b, items, 4, st)
                  : max_cols <= goldi::RATE
-                 ? launch_batch("leaf_hash", goldi::k_leaf_hash_batch<true>, b, items, 1, st, status)
-                 : launch_batch("leaf_hash", goldi::k_leaf_hash_batch<false>, b, items, 1, st, status);
+                 ? launch_batch("leaf_hash", goldi::k_leaf_hash_batch<true>, b, items, 1, st)
+                 : launch_batch("leaf_hash", goldi::k_leaf_hash_batch<false>, b, items, 1, st);
     if (rc) return rc;
     // Level loop: off[k] = first node of the current child level of tree k.
     std::vector<size_t> off(nt, 0), n(nt);
@@ -325,7 +333,8 @@ int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, ui
         for (uint32_t k = 0; k < nt; k++) {
             if (n[k] <= 1) continue;
             u64 *nodes = trees[order[k]].nodes_out;
-            lb.t[m] = {nodes + off[k] * goldi::DIGEST, nodes + (off[k] + n[k]) * goldi::DIGEST, (uint32_t)n[k], 0};
+            lb.t[m] = {nodes + off[k] * goldi::DIGEST, nodes + (off[k] + n[k]) * goldi::DIGEST, nullptr,
+                       (uint32_t)n[k], 0};
             items[m] = (n[k] + 1) / 2;
             parents += items[m];
             m++;
@@ -347,10 +356,11 @@ int launch_group(const goldi_tree_t *trees, const std::vector<size_t> &order, ui
     return GOLDI_OK;
 }
 
-int launch_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
+int launch_many(const goldi_tree_t *trees, size_t n_trees, StatusMap status, hipStream_t st) {
     if (g_batch_mode.load() == 0) {
         for (size_t t = 0; t < n_trees; t++) {
-            int rc = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out, status, st);
+            int rc = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out,
+                                 status.of(t), st);
             if (rc) return rc;
         }
         return GOLDI_OK;
@@ -359,7 +369,8 @@ int launch_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hip
     std::vector<size_t> order;
     for (size_t t = 0; t < n_trees; t++) {
         if (trees[t].n_rows > 0xFFFFFFFFull || trees[t].n_cols > 0xFFFFFFFFull) {
-            int rc = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out, status, st);
+            int rc = launch_tree(trees[t].leaves, trees[t].n_rows, trees[t].n_cols, trees[t].nodes_out,
+                                 status.of(t), st);
             if (rc) return rc;
         } else {
             order.push_back(t);
@@ -388,10 +399,10 @@ std::vector<GraphEntry> g_graphs;  // most recently used last
 constexpr size_t kGraphCacheMax = 16;
 hipStream_t g_capture_stream[kMaxDevices] = {};
 
-int launch_many_graph(int dev, const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
-    std::vector<uint64_t> key = {(uint64_t)dev,        (uint64_t)(uintptr_t)status, quad_max_rows(),
-                                 quad_max_parents(), l12_max_rows(),                l12_max_parents(),
-                                 top_max_parents(),  g_batch_mode.load()};
+int launch_many_graph(int dev, const goldi_tree_t *trees, size_t n_trees, StatusMap status, hipStream_t st) {
+    std::vector<uint64_t> key = {(uint64_t)dev,      (uint64_t)(uintptr_t)status.base, status.stride,
+                                 quad_max_rows(),    quad_max_parents(),               l12_max_rows(),
+                                 l12_max_parents(),  top_max_parents(),                g_batch_mode.load()};
     for (size_t t = 0; t < n_trees; t++) {
         key.push_back((uint64_t)(uintptr_t)trees[t].leaves);
         key.push_back(trees[t].n_rows);
@@ -432,7 +443,7 @@ int launch_many_graph(int dev, const goldi_tree_t *trees, size_t n_trees, uint32
     return GOLDI_OK;
 }
 
-int enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *status, hipStream_t st) {
+int enqueue_many(const goldi_tree_t *trees, size_t n_trees, StatusMap status, hipStream_t st) {
     if (g_graph_mode.load() != 0 && g_batch_mode.load() != 0) {
         int dev = 0;
         GOLDI_HIP(hipGetDevice(&dev));
@@ -507,9 +518,9 @@ int run_sync(F enqueue) {
 
 }  // namespace
 
-int goldi_internal_enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
+int goldi_internal_enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status_per_tree,
                                 hipStream_t stream) {
-    return launch_many(trees, n_trees, dev_status, stream);
+    return launch_many(trees, n_trees, StatusMap{dev_status_per_tree, 1}, stream);
 }
 
 int goldi_internal_check_device_range(const void *p, size_t bytes, const char *what) {
@@ -525,6 +536,8 @@ const char *goldi_strerror(int code) {
         case GOLDI_ENONCANON: return "input word not canonical (>= p)";
         case GOLDI_EDEVICE: return "HIP device error";
         case GOLDI_ENOMEM: return "device allocation failed";
+        case GOLDI_ECANCELED: return "request cancelled (server destroyed while it was queued)";
+        case GOLDI_ETIMEDOUT: return "request timed out (watchdog)";
         default: return "unknown status";
     }
 }
@@ -693,13 +706,24 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
     if (rc) return rc;
     rc = check_device_range(dev_status, sizeof(uint32_t), "dev_status");
     if (rc) return rc;
-    return enqueue_many(trees, n_trees, dev_status, (hipStream_t)stream);
+    return enqueue_many(trees, n_trees, StatusMap{dev_status, 0}, (hipStream_t)stream);
+}
+
+int goldi_merkle_build_many_status_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
+                                         void *stream) {
+    int rc = validate_many(trees, n_trees);
+    if (rc) return rc;
+    size_t bytes;
+    if (mul_overflows(n_trees, sizeof(uint32_t), &bytes)) return fail(GOLDI_EINVAL, "n_trees is too large");
+    rc = check_device_range(dev_status, bytes, "dev_status");
+    if (rc) return rc;
+    return enqueue_many(trees, n_trees, StatusMap{dev_status, 1}, (hipStream_t)stream);
 }
 
 int goldi_merkle_build_many(const goldi_tree_t *trees, size_t n_trees) {
     int rc = validate_many(trees, n_trees);
     if (rc) return rc;
-    return run_sync([&](uint32_t *status) { return enqueue_many(trees, n_trees, status, 0); });
+    return run_sync([&](uint32_t *status) { return enqueue_many(trees, n_trees, StatusMap{status, 0}, 0); });
 }
 
 }  // extern "C"

@@ -303,10 +303,11 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_lane12(const u64 *__restrict__ child,
 static constexpr int MAX_BATCH = 64;
 
 struct BatchTree {
-    const u64 *src;  // leaves (column-major) or the child level
-    u64 *dst;        // digests (level 0) or the parent level
-    uint32_t n;      // rows, or children
-    uint32_t w;      // columns (leaf launches); unused for levels
+    const u64 *src;    // leaves (column-major) or the child level
+    u64 *dst;          // digests (level 0) or the parent level
+    uint32_t *status;  // this tree's status word (leaf launches); unused for levels
+    uint32_t n;        // rows, or children
+    uint32_t w;        // columns (leaf launches); unused for levels
 };
 
 struct Batch {
@@ -324,19 +325,22 @@ __device__ __forceinline__ int batch_tree_of(const Batch &b, uint32_t blk) {
     return lo;
 }
 
+// Leaf launches report a non-canonical word into the status word of the tree
+// it belongs to, so one bad tree does not mark the others of its batch.
 template <bool SINGLE>
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_batch(const Batch b, uint32_t *status) {
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_batch(const Batch b) {
     const int t = batch_tree_of(b, blockIdx.x);
     const size_t r = (size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x;
-    if (r < b.t[t].n) leaf_row<SINGLE>(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r);
+    if (r < b.t[t].n) leaf_row<SINGLE>(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, b.t[t].status, r);
 }
 
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad_batch(const Batch b, uint32_t *status) {
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad_batch(const Batch b) {
     __shared__ QuadRc tbl;
     quad_rc_load(tbl);
     const int t = batch_tree_of(b, blockIdx.x);
     const size_t r = ((size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x) >> 2;
-    if (r < b.t[t].n) leaf_row_quad(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r, threadIdx.x & 3, tbl);
+    if (r < b.t[t].n)
+        leaf_row_quad(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, b.t[t].status, r, threadIdx.x & 3, tbl);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level_batch(const Batch b) {
@@ -353,13 +357,14 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_quad_batch(const Batch b) {
     if (i < ((size_t)b.t[t].n + 1) / 2) level_node_quad(b.t[t].src, b.t[t].n, b.t[t].dst, i, threadIdx.x & 3, tbl);
 }
 
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12_batch(const Batch b, uint32_t *status) {
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12_batch(const Batch b) {
     __shared__ QuadRc tbl;
     quad_rc_load(tbl);
     const Lane12 L = lane12_setup(tbl);
     const int t = batch_tree_of(b, blockIdx.x);
     const size_t r = (size_t)(blockIdx.x - b.block_begin[t]) * LANE12_PER_BLOCK + (threadIdx.x >> 4);
-    leaf_row_lane12(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, status, r, r < b.t[t].n && L.i < WIDTH, L, tbl);
+    leaf_row_lane12(b.t[t].src, b.t[t].n, b.t[t].w, b.t[t].dst, b.t[t].status, r, r < b.t[t].n && L.i < WIDTH,
+                    L, tbl);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level_lane12_batch(const Batch b) {

@@ -13,12 +13,48 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_textbook_work_count():
-    # (8 full rounds x 12 + 22 partial) S-boxes x 4 products x 4 limb
-    # products, plus 30 dense 12 x 12 matrices x 2 limbs.
-    assert bench.MULADDS_PER_PERM == (8 * 12 + 22) * 4 * 4 + 30 * 144 * 2
+def test_work_count():
+    # The optimised form of Alg. 1: full-width products are the S-boxes'
+    # (8 full rounds x 12 + 22 partial) x 4, the pre-matrix's 11 x 11 and the
+    # 22 sparse partial matrices' 12 + 11 each, at 4 limb products each; the
+    # 8 full rounds' 12 x 12 small-entry matrices take 2 limb products per
+    # entry.
+    full = (8 * 12 + 22) * 4 + 11 * 11 + 22 * (12 + 11)
+    assert full == 1099
+    assert bench.MULADDS_PER_PERM == full * 4 + 8 * 144 * 2 == 6700
+    # The textbook form: the dense matrix in all 30 rounds.
+    assert bench.DENSE_MULADDS_PER_PERM == (8 * 12 + 22) * 4 * 4 + 30 * 144 * 2
     assert bench.perms_per_build(1 << 22, 8) == (1 << 23) - 1
     assert bench.perms_per_build(1 << 21, 256) == (1 << 21) * 32 + (1 << 21) - 1
+
+
+class _Knobs:
+    def __init__(self, **kw):
+        self.v = dict(lane12_max_rows=1 << 12, quad_max_rows=1 << 14, lane12_max_parents=1 << 12,
+                      quad_max_parents=1 << 16, top_max_parents=16)
+        self.v.update(kw)
+
+    def goldi_tune_get(self, k):
+        return self.v[k]
+
+
+def test_schedule_of_the_paper_scale_tree():
+    perms, launches = bench.schedule(_Knobs(), 1 << 22, 8)
+    assert sum(perms.values()) == bench.perms_per_build(1 << 22, 8)
+    assert launches == {"leaf_hash": 1, "leaf_hash_quad": 0, "leaf_hash_lane12": 0, "level": 5,
+                        "level_quad": 4, "level_lane12": 8, "top_lane12": 1}
+    assert perms["level"] == sum(1 << k for k in range(17, 22))
+    assert perms["top_lane12"] == 16 + 8 + 4 + 2 + 1
+
+
+def test_schedule_ragged_and_tiny():
+    for n in (1, 2, 3, 17, 1000, 4097, (1 << 20) + 3):
+        for w in (1, 8, 9, 64):
+            perms, launches = bench.schedule(_Knobs(), n, w)
+            assert sum(perms.values()) == bench.perms_per_build(n, w)
+            assert sum(launches.values()) >= 1
+    perms, launches = bench.schedule(_Knobs(top_max_parents=0), 1000, 8)
+    assert launches["top_lane12"] == 0 and perms["top_lane12"] == 0
 
 
 def test_several_gpus_refused():

@@ -153,3 +153,30 @@ def test_batched_workload_full_size(prm, knobs):
                 if idx.size:
                     pairs = np.stack([nodes[ch], nodes[ch + 1]], axis=1).reshape(-1, 4)
                     assert (nodes[offs[lvl] + idx] == oracle.merkle_level(prm, pairs)).all()
+
+
+@pytest.mark.parametrize("batch_mode", [1, 0])
+def test_per_tree_status(prm, knobs, batch_mode):
+    # One status word per tree: a non-canonical word marks its own tree only,
+    # and every other tree of the call equals the oracle.
+    import torch
+    from synth.inputs import GOLDILOCKS_P
+    knobs("batch_mode", batch_mode)
+    banner("per-tree status, batch_mode %d" % batch_mode)
+    batch = small_batch(16, 6, 4, 11, widths=(8, 9, 16))
+    n_bad, w_bad, lv_bad = batch[2]
+    lv_bad = lv_bad.copy()
+    lv_bad[(w_bad - 1) * n_bad + n_bad // 2] = np.uint64(GOLDILOCKS_P + 3)
+    batch[2] = (n_bad, w_bad, lv_bad)
+    trees = [(to_dev(lv), n, w) for n, w, lv in batch]
+    outs = [torch.empty(goldi.goldi_merkle_num_nodes(n) * 4, dtype=torch.uint64, device="cuda:0")
+            for _, n, _ in trees]
+    status = torch.zeros(len(trees), dtype=torch.int32, device="cuda:0")
+    goldi.goldi_merkle_build_many_status_async(trees, outs, status)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0, 0, 1, 0, 0, 0]
+    for k, ((n, w, lv), o) in enumerate(zip(batch, outs)):
+        if k != 2:
+            assert (to_host(o).reshape(-1, 4) == oracle.merkle_build(prm, lv, n, w)).all(), k
+    with pytest.raises(ValueError):
+        goldi.goldi_merkle_build_many_status_async(trees, outs, status[:5])

@@ -66,15 +66,30 @@ def test_buffer_too_small_rejected():
     L = goldi.lib()
     n, w = 1024, 8
     lv = to_dev(leaves_colmajor(n, w, seed=7))
-    # A separate allocation one node short of the tree.
+    status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    # A node buffer one node short, a leaf matrix one word short, a status
+    # tensor of the wrong type: the binding refuses each before any launch
+    # (torch may carve the tensor out of a larger block, which the C side,
+    # checking allocations, cannot see).
     short = torch.empty((goldi.goldi_merkle_num_nodes(n) - 1) * 4, dtype=torch.uint64, device="cuda:0")
-    rc = L.goldi_merkle_build(lv.data_ptr(), n, w, short.data_ptr())
-    # torch's caching allocator may round the block up; the check is against
-    # the allocation, so accept OK only if the block really is large enough.
-    if rc != goldi.GOLDI_OK:
-        assert rc == goldi.GOLDI_EINVAL
-    # Claiming more rows than the leaf buffer holds is always caught when the
-    # allocation is exactly sized.
+    with pytest.raises(ValueError):
+        goldi.goldi_merkle_build(lv, n, w, short)
+    with pytest.raises(ValueError):
+        goldi.goldi_merkle_build_async(lv, n, w, short, status)
+    with pytest.raises(ValueError):
+        goldi.goldi_merkle_build(lv[:-1], n, w)
+    with pytest.raises(ValueError):
+        goldi.goldi_leaf_hash(lv, n, w, torch.empty(n * 4 - 1, dtype=torch.uint64, device="cuda:0"))
+    with pytest.raises(ValueError):
+        goldi.goldi_merkle_build_many([(lv, n, w)], [short])
+    with pytest.raises(TypeError):
+        goldi.goldi_merkle_build_async(lv, n, w, torch.empty(goldi.goldi_merkle_num_nodes(n) * 4,
+                                                             dtype=torch.uint64, device="cuda:0"),
+                                       torch.zeros(1, dtype=torch.int64, device="cuda:0"))
+    with pytest.raises(TypeError):
+        goldi.goldi_merkle_build(leaves_colmajor(n, w, seed=7), n, w)
+    # Claiming more rows than the leaf buffer holds is caught by the C side
+    # too when the allocation is exactly sized.
     exact = torch.empty(n * w, dtype=torch.uint64, device="cuda:0")
     big_out = torch.empty(goldi.goldi_merkle_num_nodes(1 << 24) * 4, dtype=torch.uint64, device="cuda:0")
     assert L.goldi_merkle_build(exact.data_ptr(), 1 << 24, w, big_out.data_ptr()) == goldi.GOLDI_EINVAL
