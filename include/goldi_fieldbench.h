@@ -44,7 +44,9 @@ int goldi_fb_throughput(int op, const uint64_t *seed, uint64_t *out, size_t thre
 /* Per-opcode issue rates of the vector ALU (the isolated add/sub/multiply
  * IPC measurements of Sec. 4.3, asked of gfx950): the integer instructions the
  * field layer is built from, each written as inline assembly so that exactly
- * that instruction runs, and three 1:1 mixes. */
+ * that instruction runs, three 1:1 mixes, and forms that show what the wait
+ * states the compiler inserts after inline assembly cost.  The "block" forms
+ * always run 8 chains (chains = 1 is treated as 8 for them). */
 enum {
     GOLDI_RATE_MAD_U64_U32 = 0,  /* 32x32 + 64 -> 64, carry-out to SGPRs      */
     GOLDI_RATE_MUL_LO_U32,
@@ -68,6 +70,11 @@ enum {
     GOLDI_RATE_MIX_MAD_ADD,      /* v_mad_u64_u32 and v_add_u32, alternating   */
     GOLDI_RATE_MIX_ADDCO_ADD,    /* v_add_co_u32 and v_add_u32, alternating    */
     GOLDI_RATE_MIX_MAD_MOV,      /* v_mad_u64_u32 and v_mov_b32, alternating   */
+    GOLDI_RATE_MAD_C,            /* v_mad_u64_u32 as the compiler emits it     */
+    GOLDI_RATE_MAD_BLOCK,        /* 8 v_mad_u64_u32 in one asm statement       */
+    GOLDI_RATE_ADDCO_BLOCK,      /* 8 v_add_co_u32 in one asm statement        */
+    GOLDI_RATE_MAD_NOP_BLOCK,    /* v_mad_u64_u32 and s_nop 0, alternating,
+                                    in one asm statement                       */
     GOLDI_RATE_COUNT
 };
 

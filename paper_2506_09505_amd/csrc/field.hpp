@@ -124,11 +124,51 @@ __device__ __forceinline__ u64 reduce128(u64 lo, u64 hi) {
     return reduce128_parts(lo32(lo), hi32(lo), lo32(hi), hi32(hi));
 }
 
+#ifndef GOLDI_MUL_FOLD
+#define GOLDI_MUL_FOLD 1
+#endif
+
+#if GOLDI_MUL_FOLD && GOLDI_MUL_ASM
+// a b mod p as a weak word, with the product's middle carry folded into the
+// reduction.  With p00 = a0 b0, t = a1 b0 + hi(p00), u + c 2^64 = a0 b1 + t
+// and h = a1 b1 + hi(u), the 128-bit product is
+//     r_l + 2^64 (h + c 2^32),   r_l = lo(p00) + lo(u) 2^32,
+// and h + c 2^32 < 2^64 (the product is below 2^128), so its words are
+// r2 = lo(h) and r3 = hi(h) + c < 2^32.  Eq. 3 then gives
+//     r = r_l - hi(h) - c + r2 (2^32 - 1)   (mod p):
+// the carry c enters the subtraction as its borrow-in instead of being added
+// into h first.  The subtraction r_l - (hi(h) + c) borrows only when the
+// wrapped word is >= 2^64 - 2^32 + 1, so adding p back cannot wrap again.
+__device__ __forceinline__ u64 mul(u64 a, u64 b) {
+    const u32 a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+    const u64 p00 = mad32(a0, b0, 0);
+    const u64 t = mad32(a1, b0, hi32(p00));
+    u64 u, c;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(u), "=s"(c) : "v"(a0), "v"(b1), "v"(t));
+    const u64 h = mad32(a1, b1, hi32(u));
+    u32 y0, y1, m;
+    u64 brw;
+    asm("s_nop 1\n\t"
+        "v_subb_co_u32 %0, %2, %4, %6, %7\n\t"
+        "s_nop 1\n\t"
+        "v_subb_co_u32 %1, %2, %5, 0, %2\n\t"
+        "s_nop 1\n\t"
+        "v_subb_co_u32 %3, vcc, 0, 0, %2\n\t"
+        "v_addc_co_u32 %0, %2, %0, 0, %2\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32 %1, vcc, %1, %3, %2"
+        : "=&v"(y0), "=&v"(y1), "=&s"(brw), "=&v"(m)
+        : "v"(lo32(p00)), "v"(lo32(u)), "v"(hi32(h)), "s"(c)
+        : "vcc");
+    return mad_eps_fold(lo32(h), mk64(y0, y1));
+}
+#else
 __device__ __forceinline__ u64 mul(u64 a, u64 b) {
     u64 lo, hi;
     mul_wide(a, b, lo, hi);
     return reduce128(lo, hi);
 }
+#endif
 
 __device__ __forceinline__ u64 sqr(u64 a) { return mul(a, a); }
 

@@ -86,6 +86,8 @@ __device__ __forceinline__ void step(Regs &r, int c, u32 a, u32 b, u64 m) {
             u64 cc;
             asm volatile("v_add_co_u32 %0, %1, %0, %2" : "+v"(r.x[c]), "=s"(cc) : "v"(a));
         }
+    } else if constexpr (OP == GOLDI_RATE_MAD_C) {
+        r.y[c] = (u64)(u32)r.y[c] * b + r.y[c];  // the compiler's own v_mad_u64_u32
     } else if constexpr (OP == GOLDI_RATE_MIX_MAD_MOV) {
         if (c & 1) {
             asm volatile("v_mov_b32 %0, %1" : "=v"(r.x[c]) : "v"(r.x[c ^ 1]));
@@ -94,6 +96,48 @@ __device__ __forceinline__ void step(Regs &r, int c, u32 a, u32 b, u64 m) {
             asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(r.y[c]), "=s"(cc) : "v"(a), "v"(b));
         }
     }
+}
+
+// The block forms: the eight chains' instructions in one asm statement, so
+// the compiler inserts no wait states between them (it does after inline
+// assembly it cannot see into).
+template <int OP>
+__device__ __forceinline__ void step_block(Regs &r, u32 a, u32 b) {
+    if constexpr (OP == GOLDI_RATE_MAD_BLOCK) {
+        asm volatile(
+            "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\tv_mad_u64_u32 %1, vcc, %8, %9, %1\n\t"
+            "v_mad_u64_u32 %2, vcc, %8, %9, %2\n\tv_mad_u64_u32 %3, vcc, %8, %9, %3\n\t"
+            "v_mad_u64_u32 %4, vcc, %8, %9, %4\n\tv_mad_u64_u32 %5, vcc, %8, %9, %5\n\t"
+            "v_mad_u64_u32 %6, vcc, %8, %9, %6\n\tv_mad_u64_u32 %7, vcc, %8, %9, %7"
+            : "+v"(r.y[0]), "+v"(r.y[1]), "+v"(r.y[2]), "+v"(r.y[3]), "+v"(r.y[4]), "+v"(r.y[5]), "+v"(r.y[6]),
+              "+v"(r.y[7])
+            : "v"(a), "v"(b)
+            : "vcc");
+    } else if constexpr (OP == GOLDI_RATE_ADDCO_BLOCK) {
+        asm volatile(
+            "v_add_co_u32 %0, vcc, %0, %8\n\tv_add_co_u32 %1, vcc, %1, %8\n\t"
+            "v_add_co_u32 %2, vcc, %2, %8\n\tv_add_co_u32 %3, vcc, %3, %8\n\t"
+            "v_add_co_u32 %4, vcc, %4, %8\n\tv_add_co_u32 %5, vcc, %5, %8\n\t"
+            "v_add_co_u32 %6, vcc, %6, %8\n\tv_add_co_u32 %7, vcc, %7, %8"
+            : "+v"(r.x[0]), "+v"(r.x[1]), "+v"(r.x[2]), "+v"(r.x[3]), "+v"(r.x[4]), "+v"(r.x[5]), "+v"(r.x[6]),
+              "+v"(r.x[7])
+            : "v"(a)
+            : "vcc");
+    } else if constexpr (OP == GOLDI_RATE_MAD_NOP_BLOCK) {
+        asm volatile(
+            "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\ts_nop 0\n\tv_mad_u64_u32 %1, vcc, %8, %9, %1\n\ts_nop 0\n\t"
+            "v_mad_u64_u32 %2, vcc, %8, %9, %2\n\ts_nop 0\n\tv_mad_u64_u32 %3, vcc, %8, %9, %3\n\ts_nop 0\n\t"
+            "v_mad_u64_u32 %4, vcc, %8, %9, %4\n\ts_nop 0\n\tv_mad_u64_u32 %5, vcc, %8, %9, %5\n\ts_nop 0\n\t"
+            "v_mad_u64_u32 %6, vcc, %8, %9, %6\n\ts_nop 0\n\tv_mad_u64_u32 %7, vcc, %8, %9, %7\n\ts_nop 0"
+            : "+v"(r.y[0]), "+v"(r.y[1]), "+v"(r.y[2]), "+v"(r.y[3]), "+v"(r.y[4]), "+v"(r.y[5]), "+v"(r.y[6]),
+              "+v"(r.y[7])
+            : "v"(a), "v"(b)
+            : "vcc");
+    }
+}
+
+constexpr bool is_block(int op) {
+    return op == GOLDI_RATE_MAD_BLOCK || op == GOLDI_RATE_ADDCO_BLOCK || op == GOLDI_RATE_MAD_NOP_BLOCK;
 }
 
 template <int OP, int CH>
@@ -109,8 +153,12 @@ __global__ void __launch_bounds__(64) k_rate(u32 *out, int iters, u32 a, u32 b) 
     for (int it = 0; it < iters; it++) {
 #pragma unroll
         for (int u = 0; u < UNROLL; u++) {
+            if constexpr (is_block(OP)) {
+                step_block<OP>(r, a, b);  // always the eight chains
+            } else {
 #pragma unroll
-            for (int c = 0; c < CH; c++) step<OP>(r, c, a, b, m);
+                for (int c = 0; c < CH; c++) step<OP>(r, c, a, b, m);
+            }
         }
     }
     u32 acc = 0;
@@ -121,7 +169,7 @@ __global__ void __launch_bounds__(64) k_rate(u32 *out, int iters, u32 a, u32 b) 
 
 template <int OP>
 hipError_t launch_op(int chains, unsigned waves, int iters, u32 *out) {
-    if (chains == 1) {
+    if (chains == 1 && !is_block(OP)) {
         hipLaunchKernelGGL((k_rate<OP, 1>), dim3(waves), dim3(64), 0, 0, out, iters, 3u, 5u);
     } else {
         hipLaunchKernelGGL((k_rate<OP, 8>), dim3(waves), dim3(64), 0, 0, out, iters, 3u, 5u);
@@ -155,6 +203,10 @@ hipError_t launch(int op, int chains, unsigned waves, int iters, u32 *out) {
         GOLDI_RATE_CASE(GOLDI_RATE_MIX_MAD_ADD)
         GOLDI_RATE_CASE(GOLDI_RATE_MIX_ADDCO_ADD)
         GOLDI_RATE_CASE(GOLDI_RATE_MIX_MAD_MOV)
+        GOLDI_RATE_CASE(GOLDI_RATE_MAD_C)
+        GOLDI_RATE_CASE(GOLDI_RATE_MAD_BLOCK)
+        GOLDI_RATE_CASE(GOLDI_RATE_ADDCO_BLOCK)
+        GOLDI_RATE_CASE(GOLDI_RATE_MAD_NOP_BLOCK)
 #undef GOLDI_RATE_CASE
         default: return hipErrorInvalidValue;
     }

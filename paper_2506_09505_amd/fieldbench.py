@@ -20,7 +20,9 @@ RATE_OPS = ("v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_add_co_u32", "v_
             "v_sub_u32", "v_xor_b32", "v_mov_b32", "v_lshrrev_b32", "v_lshlrev_b64", "v_lshl_add_u64",
             "v_add3_u32", "v_mad_u32_u24", "v_cndmask_b32 (vcc)", "v_cndmask_b32_e64 (sgpr)", "v_alignbit_b32",
             "v_bfe_u32", "v_dot4_u32_u8", "mix v_mad_u64_u32 + v_add_u32", "mix v_add_co_u32 + v_add_u32",
-            "mix v_mad_u64_u32 + v_mov_b32")
+            "mix v_mad_u64_u32 + v_mov_b32", "v_mad_u64_u32 (compiler)", "v_mad_u64_u32 x8 (one asm)",
+            "v_add_co_u32 x8 (one asm)", "v_mad_u64_u32 + s_nop 0 x8 (one asm)")
+BLOCK_OPS = RATE_OPS[-3:]
 # One wave64 instruction per SIMD every 4 cycles: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz lane-instructions per second.
 FULL_RATE_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -95,6 +97,8 @@ def rates(iters: int = 2048):
         lane_ops = waves * 64 * iters * 16 * 8
         row = {"throughput_frac_of_full_rate": round(lane_ops / (ms * 1e-3) / FULL_RATE_LANE_OPS, 3)}
         for chains, key in ((1, "cycles_per_instr_one_wave_dependent"), (8, "cycles_per_instr_one_wave_8_chains")):
+            if chains == 1 and op in BLOCK_OPS:
+                continue
             it = max(1, iters // (4 if chains == 8 else 1))
             ms1 = rate_probe(op, chains, simds, it)
             row[key] = round(ms1 * 1e-3 * 2.4e9 / (it * 16 * chains), 2)
