@@ -123,6 +123,20 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
 int goldi_merkle_build_many_status_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
                                          void *stream);
 
+/* goldi_merkle_build_many for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): the same trees,
+ * the same schedule and the same outputs, but the per-tree status words live
+ * in a fixed array inside the library (one per GPU, kept until the process
+ * ends) instead of memory allocated by the call; nothing is allocated.
+ * n_trees: 1..4096 (GOLDI_EINVAL with a message beyond).  tree_status: NULL
+ * or a HOST array of n_trees codes (GOLDI_OK or GOLDI_ENONCANON per tree).
+ * The work is enqueued on `stream` (0 = null stream) and the call waits for
+ * it.  Calls on one GPU share the array: the library serialises them, and
+ * the array keeps the last call's words (each call clears its words first).
+ * Returns GOLDI_OK, GOLDI_ENONCANON if any tree held a word >= p, or the
+ * error codes of goldi_merkle_build_many. */
+int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, int *tree_status, void *stream);
+
 /* Schedule knobs (process-wide).  Every setting computes the same bytes;
  * only speed changes.  Keys:
  *   "quad_max_rows"    leaf hashing of at most this many rows runs 4 lanes per

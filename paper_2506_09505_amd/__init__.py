@@ -29,7 +29,7 @@ EXPORTS = ("goldi_poseidon_permute", "goldi_poseidon_permute_async", "goldi_merk
            "goldi_tune_set", "goldi_tune_get", "goldi_server_create", "goldi_server_submit",
            "goldi_server_wait", "goldi_server_release", "goldi_server_stats", "goldi_server_destroy",
            "goldi_admission_plan", "goldi_server_read_nodes", "goldi_profile_select",
-           "goldi_merkle_build_many_status_async", "goldi_server_set")
+           "goldi_merkle_build_many_status_async", "goldi_server_set", "goldi_merkle_build_many_noalloc")
 
 
 class GoldiError(RuntimeError):
@@ -76,6 +76,7 @@ def lib():
         L.goldi_merkle_build_many.argtypes = [ctypes.POINTER(_Tree), sz]
         L.goldi_merkle_build_many_async.argtypes = [ctypes.POINTER(_Tree), sz, vp, vp]
         L.goldi_merkle_build_many_status_async.argtypes = [ctypes.POINTER(_Tree), sz, vp, vp]
+        L.goldi_merkle_build_many_noalloc.argtypes = [ctypes.POINTER(_Tree), sz, ctypes.POINTER(ctypes.c_int), vp]
         L.goldi_strerror.argtypes = [ci]
         L.goldi_strerror.restype = ctypes.c_char_p
         L.goldi_last_error.restype = ctypes.c_char_p

@@ -516,6 +516,28 @@ int run_sync(F enqueue) {
     return GOLDI_OK;
 }
 
+// ------------------------------------------------ allocation-free builds
+// The per-tree status words of goldi_merkle_build_many_noalloc live in this
+// file-scope device array instead of memory the library allocates.  Each GPU
+// holds its own copy at its own address; host code never uses the array's
+// name (a host-side stand-in), only the address hipGetSymbolAddress returns
+// on that device.
+constexpr size_t kNoallocMaxTrees = 4096;
+static __device__ __align__(256) uint32_t scratch[kNoallocMaxTrees];
+
+struct NoallocSlot {
+    std::mutex mu;            // serialises the calls on one device
+    uint32_t *ptr = nullptr;  // device address of `scratch` on that device
+};
+NoallocSlot g_noalloc[kMaxDevices];
+
+// Clears n words (a kernel rather than a memset node, so that a captured
+// launch sequence replays correctly).
+__global__ void k_zero_words(uint32_t *p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 }  // namespace
 
 int goldi_internal_enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status_per_tree,
@@ -724,6 +746,46 @@ int goldi_merkle_build_many(const goldi_tree_t *trees, size_t n_trees) {
     int rc = validate_many(trees, n_trees);
     if (rc) return rc;
     return run_sync([&](uint32_t *status) { return enqueue_many(trees, n_trees, StatusMap{status, 0}, 0); });
+}
+
+int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, int *tree_status, void *stream) {
+    if (n_trees > kNoallocMaxTrees)
+        return fail(GOLDI_EINVAL, "goldi_merkle_build_many_noalloc: %zu trees, at most %zu (its status array is fixed)",
+                    n_trees, kNoallocMaxTrees);
+    int rc = validate_many(trees, n_trees);
+    if (rc) return rc;
+    int dev = 0;
+    GOLDI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GOLDI_EDEVICE, "device index %d out of range", dev);
+    NoallocSlot &slot = g_noalloc[dev];
+    std::lock_guard<std::mutex> lock(slot.mu);
+    if (slot.ptr == nullptr) {  // first call on this device, which is current
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(GOLDI_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        slot.ptr = (uint32_t *)p;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned zero_blocks = (unsigned)((n_trees + 255) / 256);
+    hipLaunchKernelGGL(k_zero_words, dim3(zero_blocks), dim3(256), 0, st, slot.ptr, n_trees);
+    GOLDI_HIP(hipGetLastError());
+    // Launched directly (never through the graph cache, which instantiates graphs).
+    rc = launch_many(trees, n_trees, StatusMap{slot.ptr, 1}, st);
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        return rc;
+    }
+    uint32_t words[kNoallocMaxTrees];
+    GOLDI_HIP(hipMemcpyAsync(words, slot.ptr, n_trees * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GOLDI_HIP(hipStreamSynchronize(st));
+    bool bad = false;
+    for (size_t t = 0; t < n_trees; t++) {
+        const bool b = (words[t] & goldi::STATUS_NONCANON) != 0;
+        if (tree_status) tree_status[t] = b ? GOLDI_ENONCANON : GOLDI_OK;
+        bad |= b;
+    }
+    return bad ? fail(GOLDI_ENONCANON, "an input word is >= p") : GOLDI_OK;
 }
 
 }  // extern "C"
