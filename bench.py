@@ -81,8 +81,8 @@ def perms_per_build(n_rows: int, n_cols: int) -> int:
 
 # The device code of the build kernels (their bodies, block size and
 # constants); host-side files do not change what a kernel reads or writes.
-DEVICE_SOURCES = ("field.hpp", "poseidon.hpp", "poseidon_quad.hpp", "poseidon_lane12.hpp", "kernels.hpp",
-                  "poseidon12_constants.inc")
+DEVICE_SOURCES = ("field.hpp", "field_asm.inc", "poseidon.hpp", "poseidon_quad.hpp", "poseidon_lane12.hpp",
+                  "kernels.hpp", "poseidon12_constants.inc")
 
 
 def source_digest() -> str:

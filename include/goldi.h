@@ -166,20 +166,24 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
 int goldi_tune_set(const char *key, size_t value);
 int goldi_tune_get(const char *key, size_t *value);
 
-/* Per-kernel timing for measurement; off by default.  While enabled, every
- * kernel the library launches is bracketed by two HIP events recorded on the
- * stream it is launched on.  Costs a few microseconds per launch. */
+/* Per-kernel timing for measurement; off by default.  While enabled, the
+ * kernels the library launches are timed with HIP events recorded on the
+ * stream they are launched on: each run of consecutive launches of one kind
+ * within one call (e.g. the largest levels of a tree) is bracketed by one
+ * pair of events, which also covers the gaps between those launches.  Costs a
+ * few microseconds per run. */
 int goldi_profile_enable(int on);
 
 /* Restricts the timing to one kernel kind (names as for goldi_profile_read);
  * NULL or "" times every kind again. */
 int goldi_profile_select(const char *kernel);
 
-/* Sums the elapsed times of the recorded launches of one kernel kind
+/* Sums the elapsed times of the recorded runs of one kernel kind
  * ("permute", "leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level",
- * "level_quad", "level_lane12"), waiting for them to finish, and forgets
- * them.  total_ms and count are host pointers; returns GOLDI_EINVAL for nulls
- * and GOLDI_EDEVICE if an event query fails. */
+ * "level_quad", "level_lane12", "top_lane12"), waiting for them to finish,
+ * and forgets them; *count receives the number of launches they covered.
+ * total_ms and count are host pointers; returns GOLDI_EINVAL for nulls and
+ * GOLDI_EDEVICE if an event query fails. */
 int goldi_profile_read(const char *kernel, double *total_ms, size_t *count);
 
 /* ---------------------------------------------------------------- serving

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # used by this integer code, and some of their forms are unreliable).
 HIP_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wall", "-Wno-unused-function"]
+             "-Wall", "-Wno-unused-function", "-Werror=inline-asm"]
 
 
 def sources():
@@ -47,8 +47,9 @@ def _jobs(gen_constants):
 
 def build(verbose: bool = False) -> str:
     """Compiles every library (hipcc runs in parallel, one process each)."""
-    from . import gen_constants
+    from . import gen_constants, gen_field_asm
     gen_constants.main()
+    gen_field_asm.main()
     os.makedirs(os.path.join(HERE, "_special"), exist_ok=True)
     running = []
     for out, srcs, extra in _jobs(gen_constants):

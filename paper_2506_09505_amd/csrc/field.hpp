@@ -127,6 +127,12 @@ __device__ __forceinline__ u64 reduce128(u64 lo, u64 hi) {
 #ifndef GOLDI_MUL_FOLD
 #define GOLDI_MUL_FOLD 1
 #endif
+// The same product is also available as whole inline-assembly blocks that
+// interleave two or three independent products (field_asm.inc, generated);
+// the layout with three words per lane uses them for its full rounds.
+}  // namespace goldi
+#include "field_asm.inc"
+namespace goldi {
 
 #if GOLDI_MUL_FOLD && GOLDI_MUL_ASM
 // a b mod p as a weak word, with the product's middle carry folded into the

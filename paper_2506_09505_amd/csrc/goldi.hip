@@ -94,16 +94,55 @@ int acquire_slot(int *dev_out, DeviceSlot **slot) {
 }
 
 // ------------------------------------------------------------- profiling
-// While enabled, every launch is bracketed by two HIP events recorded on the
-// launch stream; goldi_profile_read() sums their elapsed times per kernel.
+// While enabled, launches are timed with HIP events recorded on the launch
+// stream; goldi_profile_read() sums the elapsed times per kernel kind.  A run
+// of consecutive launches of one kind on one stream within one library call
+// (the five largest tree levels, say) is timed as one span: two event records
+// per run rather than per launch, so the timing disturbs the work less.  The
+// span covers the launches and the gaps between them.  It is closed by the
+// next launch of another kind or stream, and at the end of the library call.
 struct ProfRecord {
     const char *name;
     hipEvent_t start, stop;
+    size_t launches;
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::string g_prof_only;  // empty: every kernel kind
 std::vector<ProfRecord> g_prof;
+
+struct OpenSpan {
+    const char *name = nullptr;  // null: no span open
+    hipStream_t st = nullptr;
+    ProfRecord r{};
+};
+thread_local OpenSpan t_span;
+
+void span_drop() {
+    if (t_span.r.start) (void)hipEventDestroy(t_span.r.start);
+    if (t_span.r.stop) (void)hipEventDestroy(t_span.r.stop);
+    t_span = OpenSpan{};
+}
+
+int span_close() {
+    if (t_span.name == nullptr) return GOLDI_OK;
+    hipError_t e = hipEventRecord(t_span.r.stop, t_span.st);
+    if (e != hipSuccess) {
+        span_drop();
+        return fail(GOLDI_EDEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        g_prof.push_back(t_span.r);
+    }
+    t_span = OpenSpan{};
+    return GOLDI_OK;
+}
+
+// Closes the calling thread's open span when a library call returns.
+struct SpanScope {
+    ~SpanScope() { (void)span_close(); }
+};
 
 template <class F>
 int timed_launch(const char *name, hipStream_t st, F launch) {
@@ -117,27 +156,34 @@ int timed_launch(const char *name, hipStream_t st, F launch) {
         if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) on = false;
         (void)hipGetLastError();
     }
+    if (t_span.name != nullptr && (!on || strcmp(t_span.name, name) != 0 || t_span.st != st)) {
+        if (int rc = span_close()) return rc;
+    }
     if (!on) {
         launch();
         GOLDI_HIP(hipGetLastError());
         return GOLDI_OK;
     }
-    ProfRecord r{name, nullptr, nullptr};
-    // On any failure the events are released before the error is returned.
-    auto drop = [&r](const char *what, hipError_t e) {
-        if (r.start) (void)hipEventDestroy(r.start);
-        if (r.stop) (void)hipEventDestroy(r.stop);
-        return fail(GOLDI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-    };
-    hipError_t e = hipEventCreate(&r.start);
-    if (e != hipSuccess) return drop("hipEventCreate", e);
-    if ((e = hipEventCreate(&r.stop)) != hipSuccess) return drop("hipEventCreate", e);
-    if ((e = hipEventRecord(r.start, st)) != hipSuccess) return drop("hipEventRecord", e);
+    if (t_span.name == nullptr) {
+        t_span.r = ProfRecord{name, nullptr, nullptr, 0};
+        // No system-scope release at the records: the events only time device work.
+        hipError_t e = hipEventCreateWithFlags(&t_span.r.start, hipEventDisableSystemFence);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t_span.r.stop, hipEventDisableSystemFence);
+        if (e == hipSuccess) e = hipEventRecord(t_span.r.start, st);
+        if (e != hipSuccess) {
+            span_drop();
+            return fail(GOLDI_EDEVICE, "profiling event: %s", hipGetErrorString(e));
+        }
+        t_span.name = name;
+        t_span.st = st;
+    }
     launch();
-    if ((e = hipGetLastError()) != hipSuccess) return drop("kernel launch", e);
-    if ((e = hipEventRecord(r.stop, st)) != hipSuccess) return drop("hipEventRecord", e);
-    std::lock_guard<std::mutex> lock(g_prof_mu);
-    g_prof.push_back(r);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        span_drop();
+        return fail(GOLDI_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
+    }
+    t_span.r.launches++;
     return GOLDI_OK;
 }
 
@@ -505,6 +551,7 @@ int run_sync(F enqueue) {
     }
     GOLDI_HIP(hipMemsetAsync(slot->status, 0, sizeof(uint32_t), 0));
     rc = enqueue(slot->status);
+    if (rc == GOLDI_OK) rc = span_close();
     if (rc) {
         (void)hipStreamSynchronize(0);
         return rc;
@@ -542,6 +589,7 @@ __global__ void k_zero_words(uint32_t *p, size_t n) {
 
 int goldi_internal_enqueue_many(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status_per_tree,
                                 hipStream_t stream) {
+    SpanScope span_scope;
     return launch_many(trees, n_trees, StatusMap{dev_status_per_tree, 1}, stream);
 }
 
@@ -643,8 +691,10 @@ int goldi_profile_read(const char *kernel, double *total_ms, size_t *count) {
         g_prof.swap(rest);
     }
     double sum = 0.0;
+    size_t launches = 0;
     int rc = GOLDI_OK;
     for (auto &r : mine) {
+        launches += r.launches;
         float ms = 0.f;
         hipError_t e = hipEventSynchronize(r.stop);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
@@ -654,11 +704,12 @@ int goldi_profile_read(const char *kernel, double *total_ms, size_t *count) {
         (void)hipEventDestroy(r.stop);
     }
     *total_ms = sum;
-    *count = mine.size();
+    *count = launches;
     return rc;
 }
 
 int goldi_poseidon_permute_async(uint64_t *states, size_t n, uint32_t *dev_status, void *stream) {
+    SpanScope span_scope;
     int rc = validate_permute(states, n);
     if (rc) return rc;
     rc = check_device_range(dev_status, sizeof(uint32_t), "dev_status");
@@ -674,6 +725,7 @@ int goldi_poseidon_permute(uint64_t *states, size_t n) {
 
 int goldi_leaf_hash_async(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests,
                           uint32_t *dev_status, void *stream) {
+    SpanScope span_scope;
     int rc = validate_tree(leaves, n_rows, n_cols, digests, n_rows, "digests");
     if (rc) return rc;
     rc = check_device_range(dev_status, sizeof(uint32_t), "dev_status");
@@ -689,6 +741,7 @@ int goldi_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64
 
 int goldi_merkle_build_async(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes_out,
                              uint32_t *dev_status, void *stream) {
+    SpanScope span_scope;
     int rc = validate_tree(leaves, n_rows, n_cols, nodes_out, num_nodes(n_rows), "nodes_out");
     if (rc) return rc;
     rc = check_device_range(dev_status, sizeof(uint32_t), "dev_status");
@@ -724,6 +777,7 @@ static int validate_many(const goldi_tree_t *trees, size_t n_trees) {
 }
 
 int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status, void *stream) {
+    SpanScope span_scope;
     int rc = validate_many(trees, n_trees);
     if (rc) return rc;
     rc = check_device_range(dev_status, sizeof(uint32_t), "dev_status");
@@ -733,6 +787,7 @@ int goldi_merkle_build_many_async(const goldi_tree_t *trees, size_t n_trees, uin
 
 int goldi_merkle_build_many_status_async(const goldi_tree_t *trees, size_t n_trees, uint32_t *dev_status,
                                          void *stream) {
+    SpanScope span_scope;
     int rc = validate_many(trees, n_trees);
     if (rc) return rc;
     size_t bytes;
@@ -772,6 +827,7 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
     GOLDI_HIP(hipGetLastError());
     // Launched directly (never through the graph cache, which instantiates graphs).
     rc = launch_many(trees, n_trees, StatusMap{slot.ptr, 1}, st);
+    if (rc == GOLDI_OK) rc = span_close();
     if (rc) {
         (void)hipStreamSynchronize(st);
         return rc;

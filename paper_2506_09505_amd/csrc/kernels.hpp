@@ -23,6 +23,10 @@ static constexpr int BLOCK = 256;
 #ifndef GOLDI_WAVES_PER_EU
 #define GOLDI_WAVES_PER_EU 4
 #endif
+// The interleaved product blocks (field_asm.inc) use v110..v127 as scratch,
+// which lies inside the kernel's register budget only up to four waves per
+// SIMD (128 VGPRs each).
+static_assert(GOLDI_WAVES_PER_EU <= 4, "field_asm.inc scratch registers v110..v127 need a 128-VGPR budget");
 #define GOLDI_KERNEL_ATTRS __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GOLDI_WAVES_PER_EU)))
 
 __device__ __forceinline__ void report(uint32_t *status, bool bad) {

@@ -49,11 +49,27 @@ __constant__ u64 RC_SPLIT[ROUNDS + 1][WIDTH][2] = GOLDI_RC_SPLIT_INIT;
 // C[1][i] + sum_k M[i][8+k] C[0][8+k]^7 (mod p), split like RC_SPLIT.
 __constant__ u64 CAP0_RC1[WIDTH][2] = GOLDI_CAP0_RC1_INIT;
 
+// S-box x^7 = x^4 x^3 with x^2 = x x, x^3 = x^2 x, x^4 = x^2 x^2 (Alg. 1).
+// Each product is a few small statements, so the compiler can interleave the
+// S-box with independent work (the matrix terms of the other words).
 __device__ __forceinline__ u64 sbox(u64 x) {
     const u64 x2 = sqr(x);
     const u64 x3 = mul(x2, x);
     const u64 x4 = sqr(x2);
     return mul(x4, x3);
+}
+
+// Three independent S-boxes, each stage as one block of three interleaved
+// products (field_asm.inc): no wait state is spent on a carry.  Measured on
+// MI355X this helps where a lane holds three words and few waves share a
+// SIMD (the four-lanes-per-state layout) and costs 1-1.5% in the one-lane
+// layout, whose other waves already hide the wait states.
+__device__ __forceinline__ void sbox3_blocks(u64 &x, u64 &y, u64 &z) {
+    u64 x2, y2, z2, x3, y3, z3, x4, y4, z4;
+    sqr3_asm(x, y, z, x2, y2, z2);
+    mul3_asm(x2, x, y2, y, z2, z, x3, y3, z3);
+    sqr3_asm(x2, y2, z2, x4, y4, z4);
+    mul3_asm(x4, x3, y4, y3, z4, z3, x, y, z);
 }
 
 // V = a_lo + a_hi 2^32 with any a_lo and a_hi < 2^64 - 2^32, reduced to a weak word:
@@ -125,7 +141,7 @@ __device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], con
 }
 
 #ifndef GOLDI_RC_GROUP
-#define GOLDI_RC_GROUP 6  // rows per batch of round-constant loads
+#define GOLDI_RC_GROUP 4  // rows per batch of round-constant loads (2, 3, 4, 6, 12 measured; 4 best)
 #endif
 
 // Rows I0..11 with the per-row constants tbl[i] (split as in RC_SPLIT).

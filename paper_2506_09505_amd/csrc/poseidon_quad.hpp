@@ -121,8 +121,7 @@ __device__ __forceinline__ void permute_quad(u64 w[3], int q, const QuadRc &t) {
     }
 #pragma nounroll
     for (int r = 0; r < HALF_FULL; r++) {
-#pragma unroll
-        for (int k = 0; k < 3; k++) w[k] = sbox(w[k]);
+        sbox3_blocks(w[0], w[1], w[2]);
         quad_mds_add_rc(w, t.rc[r + 1] + 3 * q);
     }
     const u32 nz = q == 0 ? 0u : 0xFFFFFFFFu;
@@ -133,8 +132,7 @@ __device__ __forceinline__ void permute_quad(u64 w[3], int q, const QuadRc &t) {
     for (int r = HALF_FULL; r < HALF_FULL + PARTIAL; r++) quad_partial_round(w, t.rc[r + 1] + 3 * q, nz, m0);
 #pragma nounroll
     for (int r = HALF_FULL + PARTIAL; r < ROUNDS; r++) {
-#pragma unroll
-        for (int k = 0; k < 3; k++) w[k] = sbox(w[k]);
+        sbox3_blocks(w[0], w[1], w[2]);
         quad_mds_add_rc(w, t.rc[r + 1] + 3 * q);
     }
 }
