@@ -161,7 +161,9 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
  * compiled: how the one-state-per-lane permutation evaluates the partial
  * rounds (2 = blocks of three rounds as one product with 32-bit entries,
  * 1 = the sparse form of Sec. 2.4 / Alg. 1, 0 = the dense matrix every
- * round); goldi_tune_set rejects it with GOLDI_EINVAL.
+ * round), and "mds_limb_bits": the limb width of the full-round matrix
+ * products (32 = 32 x 32 -> 64-bit multiply-adds, 22 = 24-bit multipliers on
+ * 22-bit limbs, a test build); goldi_tune_set rejects both with GOLDI_EINVAL.
  * Returns GOLDI_EINVAL for an unknown key or a null pointer. */
 int goldi_tune_set(const char *key, size_t value);
 int goldi_tune_get(const char *key, size_t *value);

@@ -43,6 +43,10 @@ def _jobs(gen_constants):
     # form and in the dense form, so that both stay checked against the oracle.
     yield special_lib("sparse"), sources(), ["-DGOLDI_PARTIAL_FORM=1"]
     yield special_lib("dense"), sources(), ["-DGOLDI_PARTIAL_FORM=0"]
+    # Test-only: the full-round matrix on 24-bit multipliers (22-bit limbs),
+    # the alternative to the 32 x 32 -> 64-bit multiply-adds, kept checked
+    # against the oracle and timed against them.
+    yield special_lib("limb24"), sources(), ["-DGOLDI_MDS_LIMB24=1"]
 
 
 def build(verbose: bool = False) -> str:

@@ -636,8 +636,8 @@ int goldi_tune_set(const char *key, size_t value) {
     } else if (strcmp(key, "graph") == 0) {
         if (value > 1) return fail(GOLDI_EINVAL, "graph must be 0 or 1");
         g_graph_mode.store(value);
-    } else if (strcmp(key, "partial_form") == 0) {
-        return fail(GOLDI_EINVAL, "partial_form is fixed when the library is compiled");
+    } else if (strcmp(key, "partial_form") == 0 || strcmp(key, "mds_limb_bits") == 0) {
+        return fail(GOLDI_EINVAL, "%s is fixed when the library is compiled", key);
     } else {
         return fail(GOLDI_EINVAL, "goldi_tune_set: unknown key '%s'", key);
     }
@@ -662,6 +662,8 @@ int goldi_tune_get(const char *key, size_t *value) {
         *value = g_graph_mode.load();
     } else if (strcmp(key, "partial_form") == 0) {
         *value = GOLDI_USE_BLOCKS ? 2 : GOLDI_USE_SPARSE ? 1 : 0;
+    } else if (strcmp(key, "mds_limb_bits") == 0) {
+        *value = GOLDI_MDS_LIMB24 ? 22 : 32;
     } else {
         return fail(GOLDI_EINVAL, "goldi_tune_get: unknown key '%s'", key);
     }

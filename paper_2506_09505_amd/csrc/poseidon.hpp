@@ -130,6 +130,41 @@ __device__ __forceinline__ void mds_term(const u64 s[WIDTH], u64 &a_lo, u64 &a_h
     if constexpr (K + 1 < NW) mds_term<I, K + 1, NW>(s, a_lo, a_hi);
 }
 
+#ifndef GOLDI_MDS_LIMB24
+#define GOLDI_MDS_LIMB24 0
+#endif
+
+#if GOLDI_MDS_LIMB24
+// The full-round matrix on 24-bit multipliers (a test build, measured against
+// the 32 x 32 -> 64-bit form below): each word is cut into 22-bit limbs
+// l0 = bits 0..21, l1 = bits 22..43, l2 = bits 44..63, and a row's three limb
+// sums are 32-bit multiply-adds with 24-bit operands (v_mad_u32_u24); with
+// entries of at most 64 a dozen terms stay below 12 * 64 * 2^22 < 2^32.  The
+// row is then a0 + a1 2^22 + a2 2^44 = (a0 + a1 2^22) + (a2 2^12) 2^32, reduced
+// like the other rows, plus the round constant.
+__device__ __forceinline__ void limbs22(u64 x, u32 &l0, u32 &l1, u32 &l2) {
+    l0 = lo32(x) & 0x3FFFFFu;
+    l1 = __builtin_amdgcn_alignbit(hi32(x), lo32(x), 22) & 0x3FFFFFu;
+    l2 = hi32(x) >> 12;
+}
+
+template <int I, int END, int NW = WIDTH>
+__device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], const u64 (*rc)[2]) {
+    u32 l[WIDTH][3];
+#pragma unroll
+    for (int j = 0; j < NW; j++) limbs22(s[j], l[j][0], l[j][1], l[j][2]);
+    u32 a[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) a[k] = l[j][k] * GOLDI_MDS[I][j] + a[k];  // operands below 2^24: v_mad_u32_u24
+    }
+    const u64 a_lo = (u64)a[0] + ((u64)a[1] << 22);
+    const u64 a_hi = (u64)a[2] << 12;
+    out[I] = add_weak(reduce_split(a_lo, a_hi), mk64(lo32(rc[I][0]), lo32(rc[I][1])));
+    if constexpr (I + 1 < END) mds_rows<I + 1, END, NW>(s, out, rc);
+}
+#else
 template <int I, int END, int NW = WIDTH>
 __device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], const u64 (*rc)[2]) {
     constexpr int J = 1;  // the first word of mds_term's order
@@ -139,6 +174,7 @@ __device__ __forceinline__ void mds_rows(const u64 s[WIDTH], u64 out[WIDTH], con
     out[I] = reduce_split(a_lo, a_hi);
     if constexpr (I + 1 < END) mds_rows<I + 1, END, NW>(s, out, rc);
 }
+#endif
 
 #ifndef GOLDI_RC_GROUP
 #define GOLDI_RC_GROUP 4  // rows per batch of round-constant loads (2, 3, 4, 6, 12 measured; 4 best)

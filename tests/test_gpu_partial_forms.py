@@ -1,7 +1,8 @@
 """The default library evaluates the partial rounds of the one-state-per-lane
 kernels in blocks of three; the sparse form (Sec. 2.4, Alg. 1) and the dense
 form (the textbook matrix in every round) stay built as test libraries on the
-seeded instance.  Each must give the oracle's results bit for bit:
+seeded instance, and so does the full-round matrix on 24-bit multipliers
+(22-bit limbs).  Each must give the oracle's results bit for bit:
 permutations (random and edge states) and a ragged tree built with one lane
 per state at every level."""
 
@@ -19,7 +20,7 @@ from .gpu_util import banner, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 
-FORMS = ["sparse", "dense"]
+FORMS = ["sparse", "dense", "limb24"]
 
 
 def load_form(form):
@@ -37,7 +38,9 @@ def load_form(form):
     L.goldi_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(sz)]
     v = sz(99)
     assert L.goldi_tune_get(b"partial_form", ctypes.byref(v)) == 0
-    assert v.value == {"sparse": 1, "dense": 0}[form]
+    assert v.value == {"sparse": 1, "dense": 0, "limb24": 2}[form]
+    assert L.goldi_tune_get(b"mds_limb_bits", ctypes.byref(v)) == 0
+    assert v.value == (22 if form == "limb24" else 32)
     return L
 
 
