@@ -150,6 +150,18 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
  *                      of at most this many parents up to the root in one
  *                      single-workgroup launch (default 16, at most 64;
  *                      0 = one launch per level; GOLDI_EINVAL above 64);
+ *   "split_parts"      single-tree builds of at least "split_min_rows" rows
+ *                      (default 2^20) hash the leaves and build every level
+ *                      with more than "split_join_parents" parents (default
+ *                      16) as this many ranges of rows (default 2, at most 4;
+ *                      0 or 1 = no split), each on its own library-owned
+ *                      stream (created on first use per device, default
+ *                      priority), joined on the caller's stream before the
+ *                      remaining levels: the call still orders all of its work
+ *                      on `stream`.  No split while `stream` is being
+ *                      captured into a graph;
+ *   "split_min_rows", "split_join_parents"
+ *                      see "split_parts";
  *   "batch_mode"       goldi_merkle_build_many: 1 (default) = one launch per
  *                      tree level across all trees (up to 64 trees per
  *                      launch, heaviest rows first), 0 = tree after tree;

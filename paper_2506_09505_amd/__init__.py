@@ -311,7 +311,7 @@ def goldi_profile_read(kernel: str):
 
 
 TUNE_KEYS = ("quad_max_rows", "quad_max_parents", "lane12_max_rows", "lane12_max_parents", "top_max_parents",
-             "batch_mode", "graph")
+             "split_parts", "split_min_rows", "split_join_parents", "batch_mode", "graph")
 
 
 def goldi_tune_set(key: str, value: int) -> None:

@@ -240,31 +240,33 @@ size_t l12_max_parents() { return g_l12_max_parents.load(std::memory_order_relax
 size_t quad_max_rows() { return g_quad_max_rows.load(std::memory_order_relaxed); }
 size_t quad_max_parents() { return g_quad_max_parents.load(std::memory_order_relaxed); }
 
-int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests, uint32_t *status,
-                     hipStream_t st) {
+// Rows 0 .. n_rows-1 of a column-major leaf matrix whose columns are ld words
+// apart (ld = n_rows for a whole matrix, larger for a range of its rows).
+int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t ld, size_t n_cols, uint64_t *digests,
+                     uint32_t *status, hipStream_t st) {
     unsigned g;
     if (n_rows <= l12_max_rows()) {
         if (int rc = blocks_for(n_rows, 16, &g)) return rc;
         return timed_launch("leaf_hash_lane12", st, [&] {
-            hipLaunchKernelGGL(goldi::k_leaf_hash_lane12, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
-                               digests, status);
+            hipLaunchKernelGGL(goldi::k_leaf_hash_lane12, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, ld,
+                               n_cols, digests, status);
         });
     }
     if (n_rows <= quad_max_rows()) {
         if (int rc = blocks_for(n_rows, 4, &g)) return rc;
         return timed_launch("leaf_hash_quad", st, [&] {
-            hipLaunchKernelGGL(goldi::k_leaf_hash_quad, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
-                               digests, status);
+            hipLaunchKernelGGL(goldi::k_leaf_hash_quad, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, ld,
+                               n_cols, digests, status);
         });
     }
     if (int rc = blocks_for(n_rows, 1, &g)) return rc;
     return timed_launch("leaf_hash", st, [&] {
         if (n_cols <= goldi::RATE)
-            hipLaunchKernelGGL(goldi::k_leaf_hash<true>, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
-                               digests, status);
+            hipLaunchKernelGGL(goldi::k_leaf_hash<true>, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, ld,
+                               n_cols, digests, status);
         else
-            hipLaunchKernelGGL(goldi::k_leaf_hash<false>, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, n_cols,
-                               digests, status);
+            hipLaunchKernelGGL(goldi::k_leaf_hash<false>, dim3(g), dim3(goldi::BLOCK), 0, st, leaves, n_rows, ld,
+                               n_cols, digests, status);
     });
 }
 
@@ -289,11 +291,8 @@ int launch_level(const uint64_t *child, size_t n_child, uint64_t *parent, hipStr
     });
 }
 
-int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes, uint32_t *status,
-                hipStream_t st) {
-    int rc = launch_leaf_hash(leaves, n_rows, n_cols, nodes, status, st);
-    if (rc) return rc;
-    size_t off = 0, n = n_rows;
+// Levels above `off`, `n` nodes wide, up to the root, on one stream.
+int launch_upper(uint64_t *nodes, size_t off, size_t n, hipStream_t st) {
     while (n > 1) {
         if ((n + 1) / 2 <= top_max_parents()) {
             const unsigned threads = (unsigned)(64 * (((n + 1) / 2 + 3) / 4));  // whole waves of 4 states
@@ -301,12 +300,138 @@ int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *
                 hipLaunchKernelGGL(goldi::k_top_lane12, dim3(1), dim3(threads), 0, st, nodes, off, n);
             });
         }
-        rc = launch_level(nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST, st);
-        if (rc) return rc;
+        if (int rc = launch_level(nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST, st)) return rc;
         off += n;
         n = (n + 1) / 2;
     }
     return GOLDI_OK;
+}
+
+// ---------------------------------------------------------- split builds
+// A single tree's leaf hash and every level with more parents than the join
+// width (default 16: all but the tree-top launch) run as `parts` ranges of
+// rows, each on its own stream, and the streams join on the caller's stream
+// before the rest.  Two effects, both measured on the 2^22 x 8 tree (2.97 ->
+// 2.89 ms with two parts): each launch ends with a drain in which the SIMDs
+// hold fewer and fewer waves, and the other stream's launch fills them; and
+// a latency-bound level (a few thousand parents or fewer) costs about one
+// permutation latency whatever its width, so two half-width launches side by
+// side take the time of one.  Three and four parts, and unequal halves,
+// measured slower.  Part k covers leaves [b_k, b_(k+1)); every boundary is a
+// multiple of 2^depth, so at each of the first `depth` levels part k's nodes
+// are [b_k >> L, b_(k+1) >> L) of level L and every part but the last has an
+// even number of children.  The nodes written are the same as an unsplit
+// build's, byte for byte.
+std::atomic<size_t> g_split_parts{env_size("GOLDI_SPLIT_PARTS", 2)};
+std::atomic<size_t> g_split_min_rows{env_size("GOLDI_SPLIT_MIN_ROWS", (size_t)1 << 20)};
+std::atomic<size_t> g_split_join_parents{env_size("GOLDI_SPLIT_JOIN_PARENTS", 16)};
+constexpr size_t kMaxSplit = 4;
+
+// Library-owned streams (default priority, non-blocking) for parts 1.., one
+// set per device, created on first use and kept for the process's life.
+struct AuxStreams {
+    std::mutex mu;
+    hipStream_t s[kMaxSplit - 1] = {};
+    std::vector<hipEvent_t> free_events;  // fork/join events, reusable once their waits are enqueued
+};
+AuxStreams g_aux[kMaxDevices];
+
+int aux_setup(int dev, size_t parts, hipStream_t *streams, hipEvent_t *events, size_t n_events) {
+    AuxStreams &a = g_aux[dev];
+    std::lock_guard<std::mutex> lock(a.mu);
+    for (size_t k = 0; k + 1 < parts; k++) {
+        if (a.s[k] == nullptr) GOLDI_HIP(hipStreamCreateWithFlags(&a.s[k], hipStreamNonBlocking));
+        streams[k] = a.s[k];
+    }
+    for (size_t i = 0; i < n_events; i++) {
+        if (a.free_events.empty()) {
+            GOLDI_HIP(hipEventCreateWithFlags(&events[i], hipEventDisableTiming));
+        } else {
+            events[i] = a.free_events.back();
+            a.free_events.pop_back();
+        }
+    }
+    return GOLDI_OK;
+}
+
+void aux_release(int dev, const hipEvent_t *events, size_t n_events) {
+    AuxStreams &a = g_aux[dev];
+    std::lock_guard<std::mutex> lock(a.mu);
+    for (size_t i = 0; i < n_events; i++)
+        if (events[i]) a.free_events.push_back(events[i]);
+}
+
+// Number of leading levels that run split: those with more parents than the
+// join width (and than the tree-top launch takes).
+size_t split_levels(size_t n) {
+    const size_t cut = std::max(g_split_join_parents.load(), top_max_parents());
+    size_t depth = 0;
+    while ((n + 1) / 2 > cut) {
+        depth++;
+        n = (n + 1) / 2;
+    }
+    return depth;
+}
+
+int launch_split(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes, uint32_t *status,
+                 hipStream_t st, size_t parts, size_t depth) {
+    int dev = 0;
+    GOLDI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GOLDI_EDEVICE, "device index %d out of range", dev);
+    hipStream_t aux[kMaxSplit - 1] = {};
+    hipEvent_t ev[kMaxSplit] = {};  // ev[0]: fork; ev[k]: join of part k
+    if (int rc = aux_setup(dev, parts, aux, ev, parts)) return rc;
+    const size_t unit = (size_t)1 << depth;
+    size_t b[kMaxSplit + 1];
+    b[0] = 0;
+    for (size_t k = 1; k < parts; k++) b[k] = (k * n_rows / parts + unit - 1) / unit * unit;
+    b[parts] = n_rows;
+    int rc = GOLDI_OK;
+    hipError_t e = hipEventRecord(ev[0], st);
+    for (size_t k = 1; k < parts && e == hipSuccess; k++) e = hipStreamWaitEvent(aux[k - 1], ev[0], 0);
+    if (e != hipSuccess) rc = fail(GOLDI_EDEVICE, "split fork: %s", hipGetErrorString(e));
+    size_t off_end = 0, n_end = n_rows;  // level `depth`: offset and width
+    for (size_t k = 0; k < parts && rc == GOLDI_OK; k++) {
+        hipStream_t sk = k == 0 ? st : aux[k - 1];
+        rc = launch_leaf_hash(leaves + b[k], b[k + 1] - b[k], n_rows, n_cols, nodes + b[k] * goldi::DIGEST, status,
+                              sk);
+        size_t off = 0, n = n_rows;
+        for (size_t L = 0; L < depth && rc == GOLDI_OK; L++) {
+            const size_t c0 = b[k] >> L, c1 = k + 1 < parts ? b[k + 1] >> L : n;
+            rc = launch_level(nodes + (off + c0) * goldi::DIGEST, c1 - c0, nodes + (off + n + c0 / 2) * goldi::DIGEST,
+                              sk);
+            off += n;
+            n = (n + 1) / 2;
+        }
+        off_end = off;
+        n_end = n;
+    }
+    // Join even after a failed launch, so that nothing of this call runs
+    // behind the caller's stream.
+    for (size_t k = 1; k < parts; k++) {
+        e = hipEventRecord(ev[k], aux[k - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[k], 0);
+        if (e != hipSuccess && rc == GOLDI_OK) rc = fail(GOLDI_EDEVICE, "split join: %s", hipGetErrorString(e));
+    }
+    aux_release(dev, ev, parts);
+    if (rc) return rc;
+    return launch_upper(nodes, off_end, n_end, st);
+}
+
+int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes, uint32_t *status,
+                hipStream_t st) {
+    const size_t parts = std::min(g_split_parts.load(), kMaxSplit);
+    if (parts >= 2 && n_rows >= g_split_min_rows.load()) {
+        const size_t depth = split_levels(n_rows);
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        const bool capturing = hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
+        (void)hipGetLastError();
+        // Every part needs at least 2^depth rows; a captured sequence stays on one stream.
+        if (!capturing && depth >= 1 && n_rows / parts >= ((size_t)1 << depth))
+            return launch_split(leaves, n_rows, n_cols, nodes, status, st, parts, depth);
+    }
+    if (int rc = launch_leaf_hash(leaves, n_rows, n_rows, n_cols, nodes, status, st)) return rc;
+    return launch_upper(nodes, 0, n_rows, st);
 }
 
 // ------------------------------------------------------- batched builds
@@ -630,6 +755,13 @@ int goldi_tune_set(const char *key, size_t value) {
         if (value > (size_t)goldi::TOP_STATES)
             return fail(GOLDI_EINVAL, "top_max_parents must be at most %d", goldi::TOP_STATES);
         g_top_max_parents.store(value);
+    } else if (strcmp(key, "split_parts") == 0) {
+        if (value > kMaxSplit) return fail(GOLDI_EINVAL, "split_parts must be at most %zu", kMaxSplit);
+        g_split_parts.store(value);
+    } else if (strcmp(key, "split_min_rows") == 0) {
+        g_split_min_rows.store(value);
+    } else if (strcmp(key, "split_join_parents") == 0) {
+        g_split_join_parents.store(value);
     } else if (strcmp(key, "batch_mode") == 0) {
         if (value > 1) return fail(GOLDI_EINVAL, "batch_mode must be 0 or 1");
         g_batch_mode.store(value);
@@ -656,6 +788,12 @@ int goldi_tune_get(const char *key, size_t *value) {
         *value = l12_max_parents();
     } else if (strcmp(key, "top_max_parents") == 0) {
         *value = top_max_parents();
+    } else if (strcmp(key, "split_parts") == 0) {
+        *value = g_split_parts.load();
+    } else if (strcmp(key, "split_min_rows") == 0) {
+        *value = g_split_min_rows.load();
+    } else if (strcmp(key, "split_join_parents") == 0) {
+        *value = g_split_join_parents.load();
     } else if (strcmp(key, "batch_mode") == 0) {
         *value = g_batch_mode.load();
     } else if (strcmp(key, "graph") == 0) {
@@ -732,13 +870,14 @@ int goldi_leaf_hash_async(const uint64_t *leaves, size_t n_rows, size_t n_cols, 
     if (rc) return rc;
     rc = check_device_range(dev_status, sizeof(uint32_t), "dev_status");
     if (rc) return rc;
-    return launch_leaf_hash(leaves, n_rows, n_cols, digests, dev_status, (hipStream_t)stream);
+    return launch_leaf_hash(leaves, n_rows, n_rows, n_cols, digests, dev_status, (hipStream_t)stream);
 }
 
 int goldi_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *digests) {
     int rc = validate_tree(leaves, n_rows, n_cols, digests, n_rows, "digests");
     if (rc) return rc;
-    return run_sync([&](uint32_t *status) { return launch_leaf_hash(leaves, n_rows, n_cols, digests, status, 0); });
+    return run_sync(
+        [&](uint32_t *status) { return launch_leaf_hash(leaves, n_rows, n_rows, n_cols, digests, status, 0); });
 }
 
 int goldi_merkle_build_async(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes_out,

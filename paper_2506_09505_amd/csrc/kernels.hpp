@@ -44,12 +44,13 @@ __device__ __forceinline__ void store_digest(u64 *dst, const u64 s[WIDTH]) {
 
 // Leaf linear hash of row r (Sec. 2.4 sponge, Sec. 4.2 leaves): the row of
 // the column-major matrix is absorbed in chunks of 8 words; lane r reads
-// leaves[c*n_rows + r], so a wave's loads of one column are contiguous.
+// leaves[c*ld + r] (ld: the column stride, the matrix's full row count), so a
+// wave's loads of one column are contiguous.
 // SINGLE: the caller guarantees n_cols <= 8, so the row is one absorption of
 // a zero-capacity state and only the digest is kept (the permutation skips
 // the constant S-boxes of round 0 and rows 4..11 of the last matrix).
 template <bool SINGLE>
-__device__ __forceinline__ void leaf_row(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+__device__ __forceinline__ void leaf_row(const u64 *__restrict__ leaves, size_t ld, size_t n_cols,
                                          u64 *__restrict__ digests, uint32_t *status, size_t r) {
     u64 s[WIDTH];
 #pragma unroll
@@ -59,7 +60,7 @@ __device__ __forceinline__ void leaf_row(const u64 *__restrict__ leaves, size_t 
 #pragma unroll
         for (int k = 0; k < RATE; k++) {
             if (k < (int)n_cols) {
-                const u64 w = leaves[(size_t)k * n_rows + r];
+                const u64 w = leaves[(size_t)k * ld + r];
                 bad |= w >= P;
                 s[k] = w;
             }
@@ -70,7 +71,7 @@ __device__ __forceinline__ void leaf_row(const u64 *__restrict__ leaves, size_t 
 #pragma unroll
             for (int k = 0; k < RATE; k++) {
                 if (c0 + k < n_cols) {
-                    const u64 w = leaves[(c0 + k) * n_rows + r];
+                    const u64 w = leaves[(c0 + k) * ld + r];
                     bad |= w >= P;
                     s[k] = add_weak(s[k], w);
                 }
@@ -117,7 +118,7 @@ __device__ __forceinline__ void store_digest_quad(u64 *d, const u64 w[3], int q)
     }
 }
 
-__device__ __forceinline__ void leaf_row_quad(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+__device__ __forceinline__ void leaf_row_quad(const u64 *__restrict__ leaves, size_t ld, size_t n_cols,
                                               u64 *__restrict__ digests, uint32_t *status, size_t r, int q,
                                               const QuadRc &tbl) {
     u64 w[3] = {0, 0, 0};
@@ -127,7 +128,7 @@ __device__ __forceinline__ void leaf_row_quad(const u64 *__restrict__ leaves, si
         for (int k = 0; k < 3; k++) {
             const int idx = 3 * q + k;
             if (idx < RATE && c0 + idx < n_cols) {
-                const u64 v = leaves[(c0 + idx) * n_rows + r];
+                const u64 v = leaves[(c0 + idx) * ld + r];
                 bad |= v >= P;
                 w[k] = add_weak(w[k], v);
             }
@@ -159,14 +160,14 @@ __device__ __forceinline__ void level_node_quad(const u64 *__restrict__ child, s
 // Every lane must reach the permutation (it reads other lanes), so range
 // checks guard only loads and stores.
 
-__device__ __forceinline__ void leaf_row_lane12(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
+__device__ __forceinline__ void leaf_row_lane12(const u64 *__restrict__ leaves, size_t ld, size_t n_cols,
                                                 u64 *__restrict__ digests, uint32_t *status, size_t r, bool valid,
                                                 const Lane12 &L, const QuadRc &tbl) {
     u64 x = 0;
     bool bad = false;
     for (size_t c0 = 0; c0 < n_cols; c0 += RATE) {
         if (valid && L.i < RATE && c0 + L.i < n_cols) {
-            const u64 v = leaves[(c0 + L.i) * n_rows + r];
+            const u64 v = leaves[(c0 + L.i) * ld + r];
             bad |= v >= P;
             x = add_weak(x, v);
         }
@@ -209,11 +210,13 @@ __global__ void GOLDI_KERNEL_ATTRS k_permute(u64 *states, size_t n, uint32_t *st
     for (int k = 0; k < WIDTH; k++) p[k] = canon(s[k]);
 }
 
+// Rows 0 .. n_rows-1 of a column-major matrix whose columns are ld words
+// apart (ld >= n_rows: a range of rows of a taller matrix).
 template <bool SINGLE>
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
-                                               u64 *__restrict__ digests, uint32_t *status) {
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash(const u64 *__restrict__ leaves, size_t n_rows, size_t ld,
+                                               size_t n_cols, u64 *__restrict__ digests, uint32_t *status) {
     const size_t r = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (r < n_rows) leaf_row<SINGLE>(leaves, n_rows, n_cols, digests, status, r);
+    if (r < n_rows) leaf_row<SINGLE>(leaves, ld, n_cols, digests, status, r);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level(const u64 *__restrict__ child, size_t n_child, u64 *__restrict__ parent) {
@@ -221,12 +224,12 @@ __global__ void GOLDI_KERNEL_ATTRS k_level(const u64 *__restrict__ child, size_t
     if (i < (n_child + 1) / 2) level_node(child, n_child, parent, i);
 }
 
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
-                                                    u64 *__restrict__ digests, uint32_t *status) {
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad(const u64 *__restrict__ leaves, size_t n_rows, size_t ld,
+                                                    size_t n_cols, u64 *__restrict__ digests, uint32_t *status) {
     __shared__ QuadRc tbl;
     quad_rc_load(tbl);
     const size_t r = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
-    if (r < n_rows) leaf_row_quad(leaves, n_rows, n_cols, digests, status, r, threadIdx.x & 3, tbl);
+    if (r < n_rows) leaf_row_quad(leaves, ld, n_cols, digests, status, r, threadIdx.x & 3, tbl);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, size_t n_child,
@@ -279,13 +282,13 @@ __global__ void __launch_bounds__(TOP_THREADS) k_top_lane12(u64 *nodes, size_t o
     }
 }
 
-__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12(const u64 *__restrict__ leaves, size_t n_rows, size_t n_cols,
-                                                      u64 *__restrict__ digests, uint32_t *status) {
+__global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12(const u64 *__restrict__ leaves, size_t n_rows, size_t ld,
+                                                      size_t n_cols, u64 *__restrict__ digests, uint32_t *status) {
     __shared__ QuadRc tbl;
     quad_rc_load(tbl);
     const Lane12 L = lane12_setup(tbl);
     const size_t r = (size_t)blockIdx.x * LANE12_PER_BLOCK + (threadIdx.x >> 4);
-    leaf_row_lane12(leaves, n_rows, n_cols, digests, status, r, r < n_rows && L.i < WIDTH, L, tbl);
+    leaf_row_lane12(leaves, ld, n_cols, digests, status, r, r < n_rows && L.i < WIDTH, L, tbl);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level_lane12(const u64 *__restrict__ child, size_t n_child,

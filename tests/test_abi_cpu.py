@@ -67,6 +67,19 @@ def test_every_documented_knob_reads_back():
         assert goldi.goldi_tune_get(k) == v
 
 
+def test_split_knob_bounds():
+    old = goldi.goldi_tune_get("split_parts")
+    try:
+        for parts in (0, 1, 2, 3, 4):
+            goldi.goldi_tune_set("split_parts", parts)
+            assert goldi.goldi_tune_get("split_parts") == parts
+        with pytest.raises(goldi.GoldiError):
+            goldi.goldi_tune_set("split_parts", 5)
+        assert goldi.goldi_tune_get("split_parts") == 4
+    finally:
+        goldi.goldi_tune_set("split_parts", old)
+
+
 @pytest.mark.parametrize("name,form", [(None, 2), ("sparse", 1), ("dense", 0)])
 def test_partial_form_of_each_build(name, form):
     # The default library takes the partial rounds in blocks; the test-only

@@ -113,7 +113,8 @@ def test_dispatch_limit():
     # One dispatch covers at most 2^32 - 1 work-items.  Too many states is
     # refused before any buffer is inspected; a tree whose row count times the
     # lanes per row (forced to 16 by the one-word-per-lane knob) crosses the
-    # limit is refused at its first launch, so nothing runs.
+    # limit is refused at its first launch, so nothing runs.  (Unsplit: split
+    # in two, each half's launch would stay below the limit.)
     import torch
     L = goldi.lib()
     d = to_dev(uniform_states(4, seed=8))
@@ -122,11 +123,14 @@ def test_dispatch_limit():
     lv = torch.empty(n, dtype=torch.uint64, device="cuda:0")
     out = torch.empty(goldi.goldi_merkle_num_nodes(n) * 4, dtype=torch.uint64, device="cuda:0")
     old = goldi.goldi_tune_get("lane12_max_rows")
+    old_split = goldi.goldi_tune_get("split_parts")
     try:
         goldi.goldi_tune_set("lane12_max_rows", 1 << 40)
+        goldi.goldi_tune_set("split_parts", 0)
         assert L.goldi_merkle_build(lv.data_ptr(), n, 1, out.data_ptr()) == goldi.GOLDI_EINVAL
         assert b"dispatch" in L.goldi_last_error()
     finally:
         goldi.goldi_tune_set("lane12_max_rows", old)
+        goldi.goldi_tune_set("split_parts", old_split)
     del lv, out
     torch.cuda.empty_cache()
