@@ -219,12 +219,14 @@ def main() -> int:
     return bench_tree(args, goldi, np, torch)
 
 
-KINDS = ("leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level", "level_quad", "level_lane12", "top_lane12")
+KINDS = ("leaf_hash", "leaf_hash_quad", "leaf_hash_lane12", "level", "level_quad", "levels_lane12", "top_lane12")
+LEVELS_PER_LAUNCH = 5  # one-word-per-lane launches below the top: up to five levels each
 
 
 def schedule(goldi, n_rows: int, n_cols: int):
-    """Permutations and launches per kernel kind of one build, following the
-    library's schedule knobs (an unpaired last node is moved, not hashed)."""
+    """Permutations and launches per kernel kind of one build on one stream,
+    following the library's schedule knobs (an unpaired last node is moved,
+    not hashed)."""
     t = {k: goldi.goldi_tune_get(k) for k in ("lane12_max_rows", "quad_max_rows", "lane12_max_parents",
                                                "quad_max_parents", "top_max_parents")}
     perms = dict.fromkeys(KINDS, 0)
@@ -233,18 +235,21 @@ def schedule(goldi, n_rows: int, n_cols: int):
             "leaf_hash_quad" if n_rows <= t["quad_max_rows"] else "leaf_hash")
     perms[leaf] += n_rows * ((n_cols + 7) // 8)
     launches[leaf] += 1
-    n, top = n_rows, False
+    n = n_rows
     while n > 1:
         par = (n + 1) // 2
-        if not top and par <= t["top_max_parents"]:
-            top = True
-            launches["top_lane12"] += 1
-        kind = ("top_lane12" if top else "level_lane12" if par <= t["lane12_max_parents"] else
-                "level_quad" if par <= t["quad_max_parents"] else "level")
-        perms[kind] += n // 2
-        if not top:
-            launches[kind] += 1
-        n = par
+        if par <= t["top_max_parents"]:
+            kind, levels = "top_lane12", 64
+        elif par <= t["lane12_max_parents"]:
+            kind, levels = "levels_lane12", LEVELS_PER_LAUNCH
+        else:
+            kind, levels = ("level_quad" if par <= t["quad_max_parents"] else "level"), 1
+        launches[kind] += 1
+        for _ in range(levels):
+            if n == 1:
+                break
+            perms[kind] += n // 2
+            n = (n + 1) // 2
     return perms, launches
 
 

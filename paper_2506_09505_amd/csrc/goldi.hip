@@ -230,9 +230,9 @@ std::atomic<size_t> g_graph_mode{env_size("GOLDI_GRAPH_MODE", 0)};
 // latency still, more instructions in total).
 std::atomic<size_t> g_l12_max_rows{env_size("GOLDI_LANE12_MAX_ROWS", (size_t)1 << 12)};
 std::atomic<size_t> g_l12_max_parents{env_size("GOLDI_LANE12_MAX_PARENTS", (size_t)1 << 12)};
-// Single-tree builds finish in one launch (k_top_lane12) from the first level
-// of at most this many parents (<= 64; the default 16 keeps one wave per
-// SIMD of the workgroup's CU); 0 disables.
+// Single-tree builds finish in one single-workgroup launch (k_levels_lane12)
+// from the first level of at most this many parents (<= 64; the default 16
+// keeps one wave per SIMD of the workgroup's CU); 0 disables.
 std::atomic<size_t> g_top_max_parents{env_size("GOLDI_TOP_MAX_PARENTS", 16)};
 size_t top_max_parents() { return g_top_max_parents.load(std::memory_order_relaxed); }
 size_t l12_max_rows() { return g_l12_max_rows.load(std::memory_order_relaxed); }
@@ -270,16 +270,14 @@ int launch_leaf_hash(const uint64_t *leaves, size_t n_rows, size_t ld, size_t n_
     });
 }
 
-int launch_level(const uint64_t *child, size_t n_child, uint64_t *parent, hipStream_t st) {
+// One level, one lane (or four) per state; the one-word-per-lane layout runs
+// several levels per launch instead (launch_levels_lane12).  The layout
+// follows `width_par` parents (default: this launch's own), so that the
+// ranges of a split level take the layout of the whole level.
+int launch_level(const uint64_t *child, size_t n_child, uint64_t *parent, hipStream_t st, size_t width_par = 0) {
     const size_t n_par = (n_child + 1) / 2;
     unsigned g;
-    if (n_par <= l12_max_parents()) {
-        if (int rc = blocks_for(n_par, 16, &g)) return rc;
-        return timed_launch("level_lane12", st, [&] {
-            hipLaunchKernelGGL(goldi::k_level_lane12, dim3(g), dim3(goldi::BLOCK), 0, st, child, n_child, parent);
-        });
-    }
-    if (n_par <= quad_max_parents()) {
+    if ((width_par ? width_par : n_par) <= quad_max_parents()) {
         if (int rc = blocks_for(n_par, 4, &g)) return rc;
         return timed_launch("level_quad", st, [&] {
             hipLaunchKernelGGL(goldi::k_level_quad, dim3(g), dim3(goldi::BLOCK), 0, st, child, n_child, parent);
@@ -291,14 +289,41 @@ int launch_level(const uint64_t *child, size_t n_child, uint64_t *parent, hipStr
     });
 }
 
+// Levels of one word per lane: from the level at `off` (n nodes wide), its
+// nodes [c0, c1), through `levels` <= kLevelsPerLaunch levels in one launch
+// of 256-thread blocks (32 nodes per block: c0, and c1 unless it is n, must
+// be multiples of 2^levels).
+constexpr int kLevelsPerLaunch = 5;
+int launch_levels_lane12(uint64_t *nodes, size_t off, size_t n, size_t c0, size_t c1, int levels, hipStream_t st) {
+    unsigned g;
+    if (int rc = blocks_for((c1 - c0 + 1) / 2, 16, &g)) return rc;
+    return timed_launch("levels_lane12", st, [&] {
+        hipLaunchKernelGGL(goldi::k_levels_lane12, dim3(g), dim3(goldi::BLOCK), 0, st, nodes, off, n, c0, c1, levels);
+    });
+}
+
+// Every level from the one at `off` (n nodes, at most 2 TOP_STATES) to the
+// root in one single-workgroup launch, sized to the first level's parents.
+int launch_top(uint64_t *nodes, size_t off, size_t n, hipStream_t st) {
+    const unsigned threads = (unsigned)(64 * (((n + 1) / 2 + 3) / 4));  // whole waves of 4 states
+    return timed_launch("top_lane12", st, [&] {
+        hipLaunchKernelGGL(goldi::k_levels_lane12, dim3(1), dim3(threads), 0, st, nodes, off, n, (size_t)0, n,
+                           64);
+    });
+}
+
 // Levels above `off`, `n` nodes wide, up to the root, on one stream.
 int launch_upper(uint64_t *nodes, size_t off, size_t n, hipStream_t st) {
     while (n > 1) {
-        if ((n + 1) / 2 <= top_max_parents()) {
-            const unsigned threads = (unsigned)(64 * (((n + 1) / 2 + 3) / 4));  // whole waves of 4 states
-            return timed_launch("top_lane12", st, [&] {
-                hipLaunchKernelGGL(goldi::k_top_lane12, dim3(1), dim3(threads), 0, st, nodes, off, n);
-            });
+        const size_t n_par = (n + 1) / 2;
+        if (n_par <= top_max_parents()) return launch_top(nodes, off, n, st);
+        if (n_par <= l12_max_parents()) {
+            if (int rc = launch_levels_lane12(nodes, off, n, 0, n, kLevelsPerLaunch, st)) return rc;
+            for (int k = 0; k < kLevelsPerLaunch && n > 1; k++) {
+                off += n;
+                n = (n + 1) / 2;
+            }
+            continue;
         }
         if (int rc = launch_level(nodes + off * goldi::DIGEST, n, nodes + (off + n) * goldi::DIGEST, st)) return rc;
         off += n;
@@ -396,12 +421,25 @@ int launch_split(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t 
         rc = launch_leaf_hash(leaves + b[k], b[k + 1] - b[k], n_rows, n_cols, nodes + b[k] * goldi::DIGEST, status,
                               sk);
         size_t off = 0, n = n_rows;
-        for (size_t L = 0; L < depth && rc == GOLDI_OK; L++) {
+        for (size_t L = 0; L < depth && rc == GOLDI_OK;) {
             const size_t c0 = b[k] >> L, c1 = k + 1 < parts ? b[k + 1] >> L : n;
-            rc = launch_level(nodes + (off + c0) * goldi::DIGEST, c1 - c0, nodes + (off + n + c0 / 2) * goldi::DIGEST,
-                              sk);
-            off += n;
-            n = (n + 1) / 2;
+            // Latency-bound levels (one word per lane) are sized by the part's
+            // own parents: each part's launch is one permutation latency
+            // however wide its neighbour is.  The one-lane versus four-lane
+            // choice follows the whole level's width: those launches run side
+            // by side and share the GPU like one launch.
+            size_t done = 1;
+            if ((c1 - c0 + 1) / 2 <= l12_max_parents()) {
+                done = std::min((size_t)kLevelsPerLaunch, depth - L);  // c0, c1: multiples of 2^(depth - L)
+                rc = launch_levels_lane12(nodes, off, n, c0, c1, (int)done, sk);
+            } else {
+                rc = launch_level(nodes + (off + c0) * goldi::DIGEST, c1 - c0,
+                                  nodes + (off + n + c0 / 2) * goldi::DIGEST, sk, (n + 1) / 2);
+            }
+            for (size_t j = 0; j < done; j++, L++) {
+                off += n;
+                n = (n + 1) / 2;
+            }
         }
         off_end = off;
         n_end = n;

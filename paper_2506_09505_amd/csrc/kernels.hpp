@@ -242,42 +242,57 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, s
 
 static constexpr int LANE12_PER_BLOCK = BLOCK / 16;  // states per block
 
-// The top of a tree in one launch: every level from a level of at most
-// 2 TOP_STATES nodes up to the root, in one workgroup of up to TOP_THREADS
-// threads (states of 16 lanes, one word per lane; the host sizes the
-// workgroup to the first level's parents, so that few waves share a SIMD).
-// A level's nodes pass to the next level through LDS (and are written to the
-// node array); a workgroup barrier separates levels, so the top costs one
-// permutation latency per level and a single launch.  Waves with no parent
-// in a level skip its permutation (the test is the same in all their lanes).
+// Several levels of a tree in one launch, one word per lane.  The level read
+// first has n nodes at `off` of the level-major node array; the launch covers
+// its nodes [c0, c1).  Block b takes the 2S nodes [c0 + 2S b, ...) (S =
+// blockDim.x / 16 states, one per parent) and reduces them through up to
+// `levels` levels, or to the root: a level's nodes pass to the next through
+// LDS (and are written to the node array), a workgroup barrier separates
+// levels, and waves with no parent skip the permutation.  Blocks never read
+// each other's nodes, so they need no synchronisation: c0 and, unless it is
+// n, c1 must be multiples of 2^levels, and 2S >= 2^levels, so that every
+// parent's children lie in its own block.  Each level costs one permutation
+// latency, with one launch and one global round trip for all of them.
+// Used with 256-thread blocks and up to 5 levels for the narrow levels of a
+// tree, and as one block of up to TOP_THREADS threads for its top, from a
+// level of at most 2 TOP_STATES nodes to the root (the host sizes that
+// workgroup to the level's parents, so that few waves share a SIMD).
 static constexpr int TOP_THREADS = 1024;
 static constexpr int TOP_STATES = TOP_THREADS / 16;
 
-__global__ void __launch_bounds__(TOP_THREADS) k_top_lane12(u64 *nodes, size_t off, size_t n) {
+__global__ void __launch_bounds__(TOP_THREADS) k_levels_lane12(u64 *nodes, size_t off, size_t n, size_t c0,
+                                                               size_t c1, int levels) {
     __shared__ QuadRc tbl;
     __shared__ u64 buf[2][2 * TOP_STATES * DIGEST];
     quad_rc_load(tbl);
     const Lane12 L = lane12_setup(tbl);
-    const int p = threadIdx.x >> 4;        // the state (parent) this lane works on
+    const size_t S = blockDim.x >> 4;
+    const int p = threadIdx.x >> 4;             // the state (parent) this lane works on
     const int p_wave = (threadIdx.x >> 6) * 4;  // first state of this wave
-    for (size_t k = threadIdx.x; k < n * DIGEST; k += blockDim.x) buf[0][k] = nodes[off * DIGEST + k];
+    size_t lo = c0 + (size_t)blockIdx.x * 2 * S;
+    size_t hi = lo + 2 * S < c1 ? lo + 2 * S : c1;
+    for (size_t k = threadIdx.x; k < (hi - lo) * DIGEST; k += blockDim.x) buf[0][k] = nodes[(off + lo) * DIGEST + k];
     __syncthreads();
     int cur = 0;
-    while (n > 1) {  // n is the same in every thread: all reach each barrier
-        const size_t n_par = (n + 1) / 2;
-        const bool valid = (size_t)p < n_par && L.i < WIDTH;
-        const bool pair = valid && 2 * (size_t)p + 1 < n;
-        const u64 *child = buf[cur];
+    // n, lo and hi are the same in every thread of the block: all reach each barrier.
+    for (int lev = 0; lev < levels && n > 1; lev++) {
+        const size_t plo = lo / 2, phi = (hi + 1) / 2;  // this block's parents; lo is even
+        const size_t cnt = phi - plo;
+        const bool valid = (size_t)p < cnt && L.i < WIDTH;
+        const bool pair = valid && 2 * (plo + p) + 1 < n;
+        const u64 *child = buf[cur];  // parent plo + p reads local children 2p, 2p + 1
         u64 x = (pair && L.i < 2 * DIGEST) ? child[2 * p * DIGEST + L.i] : 0;
-        if ((size_t)p_wave < n_par) x = permute_lane12(x, L, tbl);  // whole waves only
+        if ((size_t)p_wave < cnt) x = permute_lane12(x, L, tbl);  // whole waves only
         if (valid && L.i < DIGEST) {
             const u64 d = pair ? canon(x) : child[2 * p * DIGEST + L.i];
             buf[cur ^ 1][p * DIGEST + L.i] = d;
-            nodes[(off + n + p) * DIGEST + L.i] = d;
+            nodes[(off + n + plo + p) * DIGEST + L.i] = d;
         }
         __syncthreads();
         off += n;
-        n = n_par;
+        n = (n + 1) / 2;
+        lo = plo;
+        hi = phi;
         cur ^= 1;
     }
 }
@@ -291,14 +306,6 @@ __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_lane12(const u64 *__restrict__ le
     leaf_row_lane12(leaves, ld, n_cols, digests, status, r, r < n_rows && L.i < WIDTH, L, tbl);
 }
 
-__global__ void GOLDI_KERNEL_ATTRS k_level_lane12(const u64 *__restrict__ child, size_t n_child,
-                                                  u64 *__restrict__ parent) {
-    __shared__ QuadRc tbl;
-    quad_rc_load(tbl);
-    const Lane12 L = lane12_setup(tbl);
-    const size_t i = (size_t)blockIdx.x * LANE12_PER_BLOCK + (threadIdx.x >> 4);
-    level_node_lane12(child, n_child, parent, i, i < (n_child + 1) / 2 && L.i < WIDTH, L, tbl);
-}
 
 // ---------------------------------------------------------------------------
 // Batched launches: one launch covers one step (the leaves, or one level) of
