@@ -348,6 +348,14 @@ int launch_upper(uint64_t *nodes, size_t off, size_t n, hipStream_t st) {
 // even number of children.  The nodes written are the same as an unsplit
 // build's, byte for byte.
 std::atomic<size_t> g_split_parts{env_size("GOLDI_SPLIT_PARTS", 2)};
+// Set while the calling thread runs a call that must not split (the
+// allocation-free entry point).
+thread_local bool t_no_split = false;
+struct NoSplitScope {
+    bool old = t_no_split;
+    NoSplitScope() { t_no_split = true; }
+    ~NoSplitScope() { t_no_split = old; }
+};
 std::atomic<size_t> g_split_min_rows{env_size("GOLDI_SPLIT_MIN_ROWS", (size_t)1 << 20)};
 std::atomic<size_t> g_split_join_parents{env_size("GOLDI_SPLIT_JOIN_PARENTS", 16)};
 constexpr size_t kMaxSplit = 4;
@@ -459,7 +467,7 @@ int launch_split(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t 
 int launch_tree(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t *nodes, uint32_t *status,
                 hipStream_t st) {
     const size_t parts = std::min(g_split_parts.load(), kMaxSplit);
-    if (parts >= 2 && n_rows >= g_split_min_rows.load()) {
+    if (parts >= 2 && n_rows >= g_split_min_rows.load() && !t_no_split) {
         const size_t depth = split_levels(n_rows);
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         const bool capturing = hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
@@ -1005,7 +1013,10 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
     hipLaunchKernelGGL(k_zero_words, dim3(zero_blocks), dim3(256), 0, st, slot.ptr, n_trees);
     GOLDI_HIP(hipGetLastError());
     // Launched directly (never through the graph cache, which instantiates graphs).
-    rc = launch_many(trees, n_trees, StatusMap{slot.ptr, 1}, st);
+    {
+        NoSplitScope no_split;  // a split would create the library's stream and events on first use
+        rc = launch_many(trees, n_trees, StatusMap{slot.ptr, 1}, st);
+    }
     if (rc == GOLDI_OK) rc = span_close();
     if (rc) {
         (void)hipStreamSynchronize(st);

@@ -101,3 +101,27 @@ def test_noalloc_allocates_nothing():
     want = goldi.goldi_merkle_build_many(batch)
     for o, w_ in zip(outs, want):
         assert (to_host(o) == to_host(w_).reshape(-1)).all()
+
+
+def test_noalloc_plain_schedule_keeps_one_stream():
+    # With batch_mode 0 the trees go through the single-tree schedule, which
+    # splits trees of 2^20 rows and more over two streams; the allocation-free
+    # entry point keeps every tree on the caller's stream, with the same bytes.
+    import torch
+    from synth import fill
+    banner("noalloc: plain schedule, a tree large enough to split elsewhere")
+    old = goldi.goldi_tune_get("batch_mode")
+    try:
+        goldi.goldi_tune_set("batch_mode", 0)
+        n, w = (1 << 20) + 5, 8
+        lv = fill.leaves_colmajor_dev(n, w, seed=35, device=torch.device("cuda:0"))
+        small = [(to_dev(lv_), n_, w_) for n_, w_, lv_ in trees_for(36, 2, 4, 9, (8,))]
+        batch = [(lv, n, w)] + small
+        outs = empty_outs(batch)
+        rc, st = noalloc(batch, outs)
+        assert rc == goldi.GOLDI_OK and st == [0, 0, 0]
+        for (d, n_, w_), o in zip(batch, outs):
+            want = goldi.goldi_merkle_build(d, n_, w_)
+            assert torch.equal(o.view(torch.int64), want.reshape(-1).view(torch.int64))
+    finally:
+        goldi.goldi_tune_set("batch_mode", old)
