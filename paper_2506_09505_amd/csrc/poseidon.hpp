@@ -72,14 +72,27 @@ __device__ __forceinline__ void sbox3_blocks(u64 &x, u64 &y, u64 &z) {
     mul3_asm(x4, x3, y4, y3, z4, z3, x, y, z);
 }
 
-// V = a_lo + a_hi 2^32 with any a_lo and a_hi < 2^64 - 2^32, reduced to a weak word:
-// V = w2 2^64 + (w1 2^32 + lo32(a_lo)) with w1 = hi32(a_lo) + lo32(a_hi)
-// and w2 = hi32(a_hi) + carry, then 2^64 = 2^32 - 1.
+// V = a_lo + a_hi 2^32 with a_lo, a_hi < 2^63 (every row accumulator of
+// this library stays below 2^58), reduced to a weak word.  With
+// a_hi = h1 2^32 + h0 and 2^64 = 2^32 - 1 (mod p):
+//     V = (a_lo + h1 (2^32 - 1)) + h0 2^32.
+// The bracket is one multiply-add and cannot overflow (h1 < 2^31).  Adding
+// h0 into its high word may carry out of 64 bits; the wrapped word is then
+// below 2^64 - 2^32, so the carry's 2^32 - 1 is added back with a
+// multiply-add that cannot overflow.  Four instructions.
 __device__ __forceinline__ u64 reduce_split(u64 a_lo, u64 a_hi) {
-    u32 c, junk;
-    const u32 w1 = __builtin_addc(hi32(a_lo), lo32(a_hi), 0u, &c);
-    const u32 w2 = __builtin_addc(hi32(a_hi), 0u, c, &junk);
-    return mad_eps_fold(w2, mk64(lo32(a_lo), w1));
+    u64 r;
+    asm("v_mad_u64_u32 %0, vcc, %1, -1, %2" : "=v"(r) : "v"(hi32(a_hi)), "v"(a_lo) : "vcc");
+    u32 s_hi, c;
+    asm("v_add_co_u32 %0, vcc, %2, %3\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32 %1, vcc, 0, 0, vcc"
+        : "=v"(s_hi), "=v"(c)
+        : "v"(hi32(r)), "v"(lo32(a_hi))
+        : "vcc");
+    u64 out;
+    asm("v_mad_u64_u32 %0, vcc, %1, -1, %2" : "=v"(out) : "v"(c), "v"(mk64(lo32(r), s_hi)) : "vcc");
+    return out;
 }
 
 // m * x + acc for a matrix entry m (an inline constant, 1..64) as exactly

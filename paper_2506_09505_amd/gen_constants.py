@@ -128,7 +128,10 @@ def sparse_form(rc, mds, half_full: int = 4, partial: int = 22):
 
 
 BLOCK = 3            # partial rounds per block
-BLOCK_ROW_SUM = 1 << 31  # bound on a block row's coefficients (see block_form)
+# Bound on a block row's coefficients (see block_form): a row adds products
+# of 32-bit limbs and a 32-bit constant half into one accumulator, which the
+# kernels' split reduction needs below 2^63: (2^31 - 2 + 1)(2^32 - 1) < 2^63.
+BLOCK_ROW_SUM = (1 << 31) - 2
 
 
 def block_form(rc, mds, k: int = BLOCK, half_full: int = 4, partial: int = 22):
@@ -150,7 +153,8 @@ def block_form(rc, mds, k: int = BLOCK, half_full: int = 4, partial: int = 22):
 
     Returns None unless every entry of A_m (m <= k), f_m and lead_b is below
     2^32 and every row's coefficients sum to at most BLOCK_ROW_SUM (so that a
-    row's products of 32-bit limbs add up in 64 bits), else a dict:
+    row's products of 32-bit limbs and its constant add up below 2^63), else a
+    dict:
       a[m]    = A_m (12 x 12 integers, column 0 zero for m >= 1), m = 0..k;
       f[m]    = f_m as f[m][i][j] (12 x m integers), m = 1..k;
       lead_b  = M P M (12 x 12 integers);

@@ -130,7 +130,7 @@ def test_accumulators_fit_64_bits():
     # Each row of a block (and of the lead round) adds products of 32-bit
     # limbs (< 2^32) by its coefficients, plus a 32-bit half of its constant,
     # in one 64-bit accumulator; the kernels' split reduction needs the sum
-    # below 2^64 - 2^32.
+    # below 2^63.
     rc, mds = load_constants()
     bf = gc.block_form(rc, mds)
     lim = (1 << 32) - 1
@@ -138,7 +138,7 @@ def test_accumulators_fit_64_bits():
     rows += [bf["lead_b"][i] + [mds[i][0]] for i in range(W)]
     for r in rows:
         assert max(r) < 1 << 32
-        assert sum(r) * lim + lim < (1 << 64) - (1 << 32)
+        assert sum(r) * lim + lim < 1 << 63
     # Four rounds per block would not fit: the generator refuses them.
     assert gc.block_form(rc, mds, k=4) is None
 

@@ -28,7 +28,9 @@ def mad_eps_fold(h, x):
 
 
 def mul_fold(a, b):
-    """The product with the middle carry folded into the reduction."""
+    """The product with the middle carry folded into the reduction and the
+    borrow fixed up before the final fold: the sequence of the generated
+    three-product blocks (field_asm.inc)."""
     a0, a1, b0, b1 = a & M32, a >> 32, b & M32, b >> 32
     p00, c0 = mad(a0, b0, 0)
     t, c1 = mad(a1, b0, p00 >> 32)
@@ -102,3 +104,90 @@ def test_fold_catches_a_dropped_carry():
     r_l = (p00 & M32) | ((u & M32) << 32)
     wrong = (r_l - (h >> 32) + (h & M32) * EPS) % P
     assert wrong != a * b % P
+
+
+def reduce_split(a_lo, a_hi):
+    """The row reduction of poseidon.hpp, for a_lo, a_hi < 2^63: r = a_lo +
+    h1 (2^32 - 1) with one multiply-add, then h0 added into r's high word
+    (carry c out of 64 bits), then c (2^32 - 1) added back."""
+    assert 0 <= a_lo < 2**63 and 0 <= a_hi < 2**63
+    h0, h1 = a_hi & M32, a_hi >> 32
+    r, c0 = mad(h1, EPS, a_lo)
+    assert c0 == 0                       # the first multiply-add never carries
+    s_hi = (r >> 32) + h0
+    c = s_hi >> 32
+    s = (r & M32) | ((s_hi & M32) << 32)
+    out, c1 = mad(c, EPS, s)
+    assert c1 == 0                       # nor does the last one
+    return out
+
+
+def test_row_reduction_edges_and_random():
+    rnd = random.Random(9)
+    edge = [0, 1, M32, M32 + 1, 2**42, 2**58 - 1, 2**62, 2**63 - 1, 2**63 - 2**32, P >> 1]
+    cases = [(a, b) for a in edge for b in edge]
+    cases += [(rnd.getrandbits(63), rnd.getrandbits(63)) for _ in range(20000)]
+    cases += [(rnd.getrandbits(43), rnd.getrandbits(43)) for _ in range(5000)]   # full-round rows
+    for a_lo, a_hi in cases:
+        r = reduce_split(a_lo, a_hi)
+        assert 0 <= r <= M64 and r % P == (a_lo + (a_hi << 32)) % P, (a_lo, a_hi)
+
+
+def test_row_reduction_needs_its_bound():
+    # Above 2^63 the first multiply-add can overflow: the bound is needed, and
+    # the generator keeps every block row below it.
+    a_lo, a_hi = M64 - 5, M64 - 5
+    _, c0 = mad(a_hi >> 32, EPS, a_lo)
+    assert c0 == 1
+
+
+def mul_merged(a, b):
+    """field.hpp's product, with the borrow's fix-up merged into the final
+    fold: y = r_l - hi(h) - c with borrow b,
+    r1 + k 2^64 = lo(h) (2^32 - 1) + y, d = k - b, r = r1 - d + d 2^32.
+    Returns (r, d)."""
+    a0, a1, b0, b1 = a & M32, a >> 32, b & M32, b >> 32
+    p00, _ = mad(a0, b0, 0)
+    t, _ = mad(a1, b0, p00 >> 32)
+    u, c = mad(a0, b1, t)
+    h, _ = mad(a1, b1, u >> 32)
+    r_l = (p00 & M32) | ((u & M32) << 32)
+    y = r_l - (h >> 32) - c
+    brw = 1 if y < 0 else 0
+    y &= M64
+    r1, k = mad(h & M32, EPS, y)
+    d = k - brw
+    assert d in (-1, 0, 1)
+    if d == -1:
+        assert (h & M32) == 0            # only when lo(h) = 0
+    # v_mad_i64_i32 d, -1, r1 (signed 64-bit result), then d into the high word
+    r2 = (r1 - d) & M64
+    r = (r2 & M32) | ((((r2 >> 32) + d) & M32) << 32)
+    assert r == r1 + d * EPS             # exact: no wrap in any case
+    return r, d
+
+
+def test_merged_product_edges_and_random():
+    rnd = random.Random(17)
+    cases = [(a, b) for a in EDGE for b in EDGE]
+    cases += [(rnd.getrandbits(64), rnd.getrandbits(64)) for _ in range(30000)]
+    seen = set()
+    for a, b in cases:
+        r, d = mul_merged(a, b)
+        seen.add(d)
+        assert 0 <= r <= M64 and r % P == a * b % P, (a, b)
+    assert {0, 1} <= seen
+
+
+def test_merged_product_negative_correction():
+    # a = s 2^48, b = t 2^48: a b = s t 2^96, so bits 64..95 are zero (lo(h) = 0)
+    # and the low word (0) is below the top part: the subtraction borrows and
+    # nothing carries, d = -1, the rarely taken case.
+    rnd = random.Random(23)
+    pairs = [(1, 1), (3, 5), (1 << 14, (1 << 15) + 1)]
+    pairs += [(rnd.randrange(1, 1 << 15), rnd.randrange(1, 1 << 15)) for _ in range(2000)]
+    for s_, t_ in pairs:
+        a, b = s_ << 48, t_ << 48
+        r, d = mul_merged(a, b)
+        assert d == -1, (s_, t_)
+        assert r % P == a * b % P
