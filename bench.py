@@ -683,20 +683,17 @@ def serve_run(srv_args, shapes, arrivals, bufs, warm):
 
 # VALU instructions per call of each function in the timed loops, counted
 # from this repository's own gfx950 code object (hipcc -S of fieldbench.hip).
-FUNCTION_VALU = {"add": 7, "sub": 6, "reduce_128_64": 9, "square_128": 15, "mult_128": 15, "mult_72": 7,
-                 "sbox": 60, "mmult_12x12_small": 365, "mmult_12x12_full": 3227}
-
-
 def bench_functions(args) -> int:
     import torch
 
-    from paper_2506_09505_amd import fieldbench
+    from paper_2506_09505_amd import count_valu, fieldbench
     torch.cuda.set_device(0)
+    valu = count_valu.read()  # written by the build from this build's own code object
     rows = {}
     for name in fieldbench.OPS:
         iters = 8 if name == "mmult_12x12_full" else 64
         rate, ms = fieldbench.throughput(name, threads=256 * 4096, iters=iters)
-        instr = FUNCTION_VALU[name]
+        instr = valu[name]
         rows[name] = {"ops_per_s": rate, "kernel_ms": round(ms, 4), "valu_per_op": instr,
                       "valu_instr_per_s_per_lane_slot": rate * instr / PEAK_MULADD_PER_S}
     out = {"metric": "Table-1 basic functions on gfx950 (ops/s)", "value": rows["mult_128"]["ops_per_s"],

@@ -51,7 +51,7 @@ def _jobs(gen_constants):
 
 def build(verbose: bool = False) -> str:
     """Compiles every library (hipcc runs in parallel, one process each)."""
-    from . import gen_constants, gen_field_asm
+    from . import count_valu, gen_constants, gen_field_asm
     gen_constants.main()
     gen_field_asm.main()
     os.makedirs(os.path.join(HERE, "_special"), exist_ok=True)
@@ -62,11 +62,21 @@ def build(verbose: bool = False) -> str:
         if verbose:
             print(" ".join(cmd), flush=True)
         running.append((out, tmp, cmd, subprocess.Popen(cmd)))
+    # The device assembly of the Table-1 functions, for their instruction counts.
+    asm_tmp = count_valu.OUT + ".s%d" % os.getpid()
+    asm_cmd = count_valu.asm_command(HIPCC, HIP_FLAGS, [os.path.join(ROOT, "include"), CSRC], asm_tmp)
+    if verbose:
+        print(" ".join(asm_cmd), flush=True)
+    asm_proc = subprocess.Popen(asm_cmd)
     failed = [cmd for out, tmp, cmd, proc in running if proc.wait() != 0]
+    if asm_proc.wait() != 0:
+        failed.append(asm_cmd)
     if failed:
         raise subprocess.CalledProcessError(1, failed[0])
     for out, tmp, cmd, proc in running:
         os.replace(tmp, out)
+    count_valu.write(asm_tmp)
+    os.remove(asm_tmp)
     return LIB
 
 

@@ -84,3 +84,19 @@ def test_profile_records_follow_the_sources(tmp_path, monkeypatch):
     rec["k_leaf_hash/tree22"]["source_digest"] = "0" * 16
     (prof / "traffic.json").write_text(json.dumps(rec))
     assert bench.traffic_from_profiles("k_leaf_hash", "tree22") is None
+
+
+def test_function_instruction_counts_from_the_build():
+    # The Table-1 instruction counts come from this build's own code object
+    # (count_valu.py, run by the build): every function is counted, and the
+    # parser takes the innermost loop of each chain kernel.
+    from paper_2506_09505_amd import count_valu
+    counts = count_valu.read()
+    assert set(counts) == set(count_valu.OPS)
+    assert all(v > 0 for v in counts.values())
+    assert counts["sbox"] == 4 * counts["mult_128"]   # x^7 is four products
+    text = "\n".join(["_ZN1x10k_fb_chainILi%dEEvv:" % op + "\n v_mov_b32 v0, 0\n.LBB0_1: ; =>This Inner Loop Header: Depth=1\n"
+                      + " v_add_u32 v1, v1, v2\n" * (8 if op < 7 else 3) + " s_cbranch_scc1 .LBB0_1\n v_mov_b32 v3, 0\n s_endpgm"
+                      for op in range(len(count_valu.OPS))])
+    got = count_valu.counts_from_asm(text)
+    assert got["add"] == 1 and got["mmult_12x12_full"] == 3
