@@ -185,7 +185,10 @@ int goldi_tune_get(const char *key, size_t *value);
  * stream they are launched on: each run of consecutive launches of one kind
  * within one call (e.g. the largest levels of a tree) is bracketed by one
  * pair of events, which also covers the gaps between those launches.  Costs a
- * few microseconds per run. */
+ * few microseconds per run.  In a split build (see "split_parts") the two
+ * halves' launches run side by side on two streams, so their runs overlap in
+ * time and a run's span includes the other stream's work; set "split_parts"
+ * to 0 to time each launch alone. */
 int goldi_profile_enable(int on);
 
 /* Restricts the timing to one kernel kind (names as for goldi_profile_read);

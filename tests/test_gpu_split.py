@@ -131,3 +131,42 @@ def test_build_captured_in_a_graph_is_not_split(prm, split):
         assert int(scratch.item()) == (1 << 20) * ((1 << 20) - 1) // 2
         assert int(status.item()) == 0
         assert (to_host(out).reshape(-1, 4) == want).all(), rep
+
+
+def test_split_builds_from_two_host_threads(prm, split):
+    # Two host threads build different trees at the same time, each on its own
+    # stream; both splits share the library's second stream and its event
+    # pool.  Each result must equal the oracle's.
+    import threading
+    import torch
+    split(2, min_rows=64, join=16)
+    shapes = [(5000, 8, 41), (4097, 9, 42)]
+    host = [(n, w, leaves_colmajor(n, w, seed=s_)) for n, w, s_ in shapes]
+    want = [oracle.merkle_build(prm, lv, n, w) for n, w, lv in host]
+    dev = [to_dev(lv) for _, _, lv in host]
+    outs = [torch.zeros(goldi.goldi_merkle_num_nodes(n) * 4, dtype=torch.uint64, device="cuda:0") for n, _, _ in host]
+    stats = [torch.zeros(1, dtype=torch.int32, device="cuda:0") for _ in host]
+    streams = [torch.cuda.Stream() for _ in host]
+    for s_ in streams:
+        s_.wait_stream(torch.cuda.current_stream())
+    errors = []
+
+    def worker(k):
+        try:
+            n, w, _ = host[k]
+            for _ in range(20):
+                goldi.goldi_merkle_build_async(dev[k], n, w, outs[k], stats[k], stream=streams[k])
+            streams[k].synchronize()
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    banner("split builds from two host threads")
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        assert int(stats[k].item()) == 0
+        assert (to_host(outs[k]).reshape(-1, 4) == want[k]).all(), k
