@@ -228,7 +228,7 @@ std::atomic<size_t> g_batch_mode{env_size("GOLDI_BATCH_MODE", 1)};
 std::atomic<size_t> g_graph_mode{env_size("GOLDI_GRAPH_MODE", 0)};
 // At or below these sizes the one-word-per-lane kernels run instead (lower
 // latency still, more instructions in total).
-std::atomic<size_t> g_l12_max_rows{env_size("GOLDI_LANE12_MAX_ROWS", (size_t)1 << 12)};
+std::atomic<size_t> g_l12_max_rows{env_size("GOLDI_LANE12_MAX_ROWS", (size_t)1 << 13)};
 std::atomic<size_t> g_l12_max_parents{env_size("GOLDI_LANE12_MAX_PARENTS", (size_t)1 << 12)};
 // Single-tree builds finish in one single-workgroup launch (k_levels_lane12)
 // from the first level of at most this many parents (<= 64; the default 16

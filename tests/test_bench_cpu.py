@@ -30,7 +30,7 @@ def test_work_count():
 
 class _Knobs:
     def __init__(self, **kw):
-        self.v = dict(lane12_max_rows=1 << 12, quad_max_rows=1 << 14, lane12_max_parents=1 << 12,
+        self.v = dict(lane12_max_rows=1 << 13, quad_max_rows=1 << 14, lane12_max_parents=1 << 12,
                       quad_max_parents=1 << 16, top_max_parents=16)
         self.v.update(kw)
 
