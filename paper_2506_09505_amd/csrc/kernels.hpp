@@ -120,7 +120,7 @@ __device__ __forceinline__ void store_digest_quad(u64 *d, const u64 w[3], int q)
 
 __device__ __forceinline__ void leaf_row_quad(const u64 *__restrict__ leaves, size_t ld, size_t n_cols,
                                               u64 *__restrict__ digests, uint32_t *status, size_t r, int q,
-                                              const QuadRc &tbl) {
+                                              const QuadTab &tbl) {
     u64 w[3] = {0, 0, 0};
     bool bad = false;
     for (size_t c0 = 0; c0 < n_cols; c0 += RATE) {
@@ -140,7 +140,7 @@ __device__ __forceinline__ void leaf_row_quad(const u64 *__restrict__ leaves, si
 }
 
 __device__ __forceinline__ void level_node_quad(const u64 *__restrict__ child, size_t n_child,
-                                                u64 *__restrict__ parent, size_t i, int q, const QuadRc &tbl) {
+                                                u64 *__restrict__ parent, size_t i, int q, const QuadTab &tbl) {
     const u64 *c = child + 2 * i * DIGEST;
     if (2 * i + 1 < n_child) {
         u64 w[3];
@@ -226,16 +226,16 @@ __global__ void GOLDI_KERNEL_ATTRS k_level(const u64 *__restrict__ child, size_t
 
 __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad(const u64 *__restrict__ leaves, size_t n_rows, size_t ld,
                                                     size_t n_cols, u64 *__restrict__ digests, uint32_t *status) {
-    __shared__ QuadRc tbl;
-    quad_rc_load(tbl);
+    __shared__ QuadTab tbl;
+    quad_tab_load(tbl);
     const size_t r = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
     if (r < n_rows) leaf_row_quad(leaves, ld, n_cols, digests, status, r, threadIdx.x & 3, tbl);
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level_quad(const u64 *__restrict__ child, size_t n_child,
                                                 u64 *__restrict__ parent) {
-    __shared__ QuadRc tbl;
-    quad_rc_load(tbl);
+    __shared__ QuadTab tbl;
+    quad_tab_load(tbl);
     const size_t i = ((size_t)blockIdx.x * BLOCK + threadIdx.x) >> 2;
     if (i < (n_child + 1) / 2) level_node_quad(child, n_child, parent, i, threadIdx.x & 3, tbl);
 }
@@ -349,8 +349,8 @@ __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_batch(const Batch b) {
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_leaf_hash_quad_batch(const Batch b) {
-    __shared__ QuadRc tbl;
-    quad_rc_load(tbl);
+    __shared__ QuadTab tbl;
+    quad_tab_load(tbl);
     const int t = batch_tree_of(b, blockIdx.x);
     const size_t r = ((size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x) >> 2;
     if (r < b.t[t].n)
@@ -364,8 +364,8 @@ __global__ void GOLDI_KERNEL_ATTRS k_level_batch(const Batch b) {
 }
 
 __global__ void GOLDI_KERNEL_ATTRS k_level_quad_batch(const Batch b) {
-    __shared__ QuadRc tbl;
-    quad_rc_load(tbl);
+    __shared__ QuadTab tbl;
+    quad_tab_load(tbl);
     const int t = batch_tree_of(b, blockIdx.x);
     const size_t i = ((size_t)(blockIdx.x - b.block_begin[t]) * BLOCK + threadIdx.x) >> 2;
     if (i < ((size_t)b.t[t].n + 1) / 2) level_node_quad(b.t[t].src, b.t[t].n, b.t[t].dst, i, threadIdx.x & 3, tbl);

@@ -51,6 +51,21 @@ def blocker():
     return fill.leaves_colmajor_dev(n, w, seed=99, stream=0), n, w
 
 
+def submit_blocker(srv):
+    """Submits the blocker and returns once the server has admitted it as a
+    group of its own (a request submitted before that could join its group).
+    Returns its id and its leaves, which must outlive the build."""
+    import time
+    b_lv, b_n, b_w = blocker()
+    groups = srv.stats()["groups"]
+    rid = srv.submit(b_lv, b_n, b_w)
+    t0 = time.monotonic()
+    while srv.stats()["groups"] == groups:
+        assert time.monotonic() - t0 < 10, "the blocker was not admitted"
+        time.sleep(1e-4)
+    return rid, b_lv
+
+
 def test_served_equals_alone_and_oracle(prm):
     banner("serving mix of 40 requests")
     reqs = make_requests(21, 40, 4, 12, (1, 8, 9, 32, 64))
@@ -107,8 +122,7 @@ def test_bad_request_fails_alone(prm):
     bad_lv = leaves_colmajor(100, 8, seed=1)
     bad_lv[17] = np.uint64(GOLDILOCKS_P)
     with goldi.GoldiServer(1 << 30, n_slots=1, max_group=8) as srv:
-        b_lv, b_n, b_w = blocker()
-        first = srv.submit(b_lv, b_n, b_w)
+        first, b_lv = submit_blocker(srv)
         ids = [srv.submit(to_dev(bad_lv), 100, 8)] + [srv.submit(src, n, w) for n, w, _, src in reqs]
         assert srv.wait(first)["status"] == 0
         bad = srv.wait(ids[0])
@@ -130,8 +144,7 @@ def test_failed_batch_is_rebuilt_alone(prm):
     reqs = make_requests(24, 5, 6, 10, (8, 32))
     with goldi.GoldiServer(1 << 30, n_slots=1, max_group=8) as srv:
         srv.set("fail_next_batches", 1)
-        b_lv, b_n, b_w = blocker()
-        first = srv.submit(b_lv, b_n, b_w)
+        first, b_lv = submit_blocker(srv)
         ids = [srv.submit(src, n, w) for n, w, _, src in reqs]
         assert srv.wait(first)["status"] == 0
         for (n, w, lv, _), rid in zip(reqs, ids):
