@@ -140,12 +140,15 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
 /* Schedule knobs (process-wide).  Every setting computes the same bytes;
  * only speed changes.  Keys:
  *   "quad_max_rows"    leaf hashing of at most this many rows runs 4 lanes per
- *                      row (lower latency, ~25% more instructions per row);
- *   "quad_max_parents" tree levels of at most this many parents do the same;
+ *                      row (default 2^14; lower latency, ~1.7x the
+ *                      instructions per row);
+ *   "quad_max_parents" tree levels of at most this many parents do the same
+ *                      (default 2^16);
  *   "lane12_max_rows", "lane12_max_parents"
- *                      at or below these sizes one state word per lane (a
- *                      16-lane row per state) is used instead: lower latency
- *                      again, more instructions in total;
+ *                      at or below these sizes (defaults 2^13 and 2^12) one
+ *                      state word per lane (a 16-lane row per state) is used
+ *                      instead: lower latency again, ~3x the instructions
+ *                      per row;
  *   "top_max_parents"  single-tree builds run every level from the first one
  *                      of at most this many parents up to the root in one
  *                      single-workgroup launch (default 16, at most 64;

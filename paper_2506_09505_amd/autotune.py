@@ -9,7 +9,7 @@ with the real kernels on the real inputs and keeps the fastest:
   directly;
 * ``quad_max_rows`` / ``quad_max_parents`` and ``lane12_max_rows`` /
   ``lane12_max_parents``: where leaf hashing and tree levels switch from one
-  lane per state (throughput) to four, then twelve lanes per state (latency).
+  lane per state (throughput) to four lanes, then one word per lane (latency).
 
 Results are cached per *shape signature* -- the sorted multiset of
 (row-count octave, chunks per row) of the batch -- in a JSON file, so batches
@@ -41,9 +41,9 @@ def signature(shapes) -> str:
 def candidates():
     for bm, gr in ((0, 0), (1, 0), (1, 1)):
         for qr, qp in itertools.product((1 << 14, 1 << 16), (1 << 16, 1 << 17)):
-            for l12 in (1 << 10, 1 << 12):
+            for l12_rows, l12_par in ((1 << 10, 1 << 10), (1 << 12, 1 << 12), (1 << 13, 1 << 12)):
                 yield {"batch_mode": bm, "graph": gr, "quad_max_rows": qr, "quad_max_parents": qp,
-                       "lane12_max_rows": l12, "lane12_max_parents": l12}
+                       "lane12_max_rows": l12_rows, "lane12_max_parents": l12_par}
 
 
 def current():
