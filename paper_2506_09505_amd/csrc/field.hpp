@@ -127,10 +127,12 @@ __device__ __forceinline__ u64 reduce128(u64 lo, u64 hi) {
 #ifndef GOLDI_MUL_FOLD
 #define GOLDI_MUL_FOLD 1
 #endif
-// Products are also available as whole inline-assembly blocks that
-// interleave three independent products (field_asm.inc, generated; there the
-// borrow is fixed up before the fold, and no wait state is spent); the
-// layout with three words per lane uses them for its full rounds.
+// Products are also available as whole inline-assembly blocks of one, two or
+// three independent products (field_asm.inc, generated from the sequence
+// below, with exactly the wait states each carry read needs: none for
+// three).  The layout with three words per lane uses the three-product
+// blocks for its full rounds, the one-word-per-lane layout the one- and
+// two-product blocks for its S-boxes.
 }  // namespace goldi
 #include "field_asm.inc"
 namespace goldi {

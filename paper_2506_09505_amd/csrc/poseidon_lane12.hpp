@@ -103,6 +103,18 @@ __device__ __forceinline__ Lane12 lane12_setup(const QuadRc &) {
     return L;
 }
 
+// The S-box with its four products as asm blocks (field_asm.inc): x^2
+// alone, x^3 and x^4 interleaved, x^7 alone.  A lone wave then spends only
+// the wait states each carry read needs (2 per block, against about 7 per
+// statement-level product, whose asm statements the compiler pads).
+__device__ __forceinline__ u64 sbox_blocks(u64 x) {
+    u64 x2, x3, x4, x7;
+    sqr1_asm(x, x2);
+    mul2_asm(x2, x, x2, x2, x3, x4);
+    mul1_asm(x4, x3, x7);
+    return x7;
+}
+
 // Word J of this lane's 16-lane row, in every lane of the row.
 template <int J>
 __device__ __forceinline__ u64 row_bcast(u64 v) {
@@ -121,7 +133,7 @@ __device__ __forceinline__ void row_terms(u64 v, const u32 (&c)[WIDTH], u64 &a_l
 
 // Full round: x <- row i of M S(x) + C[r + 1][i].
 __device__ __forceinline__ u64 lane12_full(u64 x, const u32 (&c)[WIDTH], const u64 *k) {
-    const u64 s = sbox(x);
+    const u64 s = sbox_blocks(x);
     u64 a_lo = k[0], a_hi = k[1];
     row_terms<0, WIDTH>(s, c, a_lo, a_hi);
     return reduce_split(a_lo, a_hi);
@@ -130,7 +142,7 @@ __device__ __forceinline__ u64 lane12_full(u64 x, const u32 (&c)[WIDTH], const u
 // Partial round: word 0's S-box runs while the other words' terms add up;
 // its output is broadcast from lane 0 and added last.
 __device__ __forceinline__ u64 lane12_partial(u64 x, const u32 (&c)[WIDTH], const u64 *k) {
-    const u64 s = sbox(x);
+    const u64 s = sbox_blocks(x);
     u64 a_lo = k[0], a_hi = k[1];
     row_terms<1, WIDTH>(x, c, a_lo, a_hi);
     const u64 sb = row_bcast<0>(s);
@@ -145,10 +157,10 @@ __device__ __forceinline__ u64 lane12_partial(u64 x, const u32 (&c)[WIDTH], cons
 // M P M and then add M[i][0] S(u).  c and k: this lane's lead row and
 // constant.
 __device__ __forceinline__ u64 lane12_lead(u64 x, const Lane12 &L, const u32 (&c)[WIDTH], const u64 (&k)[2]) {
-    const u64 s = sbox(x);
+    const u64 s = sbox_blocks(x);
     u64 a_lo = k[0], a_hi = k[1];
     row_terms<0, WIDTH>(s, c, a_lo, a_hi);
-    const u64 su = row_bcast<WIDTH>(sbox(reduce_split(a_lo, a_hi)));
+    const u64 su = row_bcast<WIDTH>(sbox_blocks(reduce_split(a_lo, a_hi)));
     a_lo = mad32(L.f_lead, lo32(su), a_lo);
     a_hi = mad32(L.f_lead, hi32(su), a_hi);
     return reduce_split(a_lo, a_hi);
@@ -159,7 +171,7 @@ __device__ __forceinline__ u64 lane12_lead(u64 x, const Lane12 &L, const u32 (&c
 template <int M>
 __device__ __forceinline__ void lane12_chain(const Lane12 &L, u64 &a_lo, u64 &a_hi) {
     if constexpr (M < GOLDI_BLK) {
-        const u64 sb = row_bcast<WIDTH + M - 1>(sbox(reduce_split(a_lo, a_hi)));
+        const u64 sb = row_bcast<WIDTH + M - 1>(sbox_blocks(reduce_split(a_lo, a_hi)));
         a_lo = mad32(L.f[M], lo32(sb), a_lo);
         a_hi = mad32(L.f[M], hi32(sb), a_hi);
         lane12_chain<M + 1>(L, a_lo, a_hi);
@@ -169,7 +181,7 @@ __device__ __forceinline__ void lane12_chain(const Lane12 &L, u64 &a_lo, u64 &a_
 // GOLDI_BLK partial rounds from a state holding its round constant; k is
 // this lane's constant of the block.
 __device__ __forceinline__ u64 lane12_block(u64 x, const Lane12 &L, const u64 (&k)[2]) {
-    const u64 s = sbox(x);
+    const u64 s = sbox_blocks(x);
     u64 a_lo = k[0], a_hi = k[1];
     row_terms<1, WIDTH>(x, L.b, a_lo, a_hi);
     const u64 sb = row_bcast<0>(s);

@@ -1,6 +1,5 @@
 """Writes ``csrc/field_asm.inc``: Goldilocks products as single inline-assembly
-blocks that interleave one, two or three independent products (the layout
-with three state words per lane uses the three-product blocks).
+blocks that interleave one, two or three independent products.
 
 Why: the compiler cannot see inside inline assembly, so after each asm
 statement it pads conservatively with wait states (``s_nop``), and a VALU
@@ -11,17 +10,17 @@ every carry is read at least two instructions after it was written, so no
 wait state is spent at all; with two or one, the generator inserts exactly the
 ``s_nop`` the hazard needs.
 
-Each product is the one of ``field.hpp`` (the middle carry folded into the
-reduction's borrow-in; Sec. 3.1, Eqs. 2-3: 2^64 = 2^32 - 1 mod p):
+Each product is the one of ``field.hpp`` (Sec. 3.1, Eqs. 2-3: 2^64 = 2^32 - 1
+mod p), its borrow fix-up riding in the final fold as a signed correction:
 
     p00 = a0 b0;  t = a1 b0 + hi(p00);  u + c 2^64 = a0 b1 + t;
-    h = a1 b1 + hi(u);  y = r_l - hi(h) - c (+ p on a borrow);
-    r = lo(h) (2^32 - 1) + y;  r += carry (2^32 - 1)
+    h = a1 b1 + hi(u);  y = r_l - hi(h) - c (borrow b);
+    r1 + k 2^64 = lo(h) (2^32 - 1) + y;  d = k - b;  r = r1 + d 2^32 - d
 
 The intermediate pairs live in fixed scratch VGPRs (the block must address
 the halves of 64-bit values it computes itself, which operands cannot), which
-the asm statement declares clobbered.  ``STEPS`` below is the single source of
-the instruction sequence: the header is printed from it and the CPU test
+the asm statement declares clobbered.  ``STEPS`` below is the single source
+of the instruction sequence: the header is printed from it, and the CPU test
 (tests/test_field_asm.py) replays it with exact integers, checks every hazard
 distance and that only declared registers are touched.
 
@@ -39,21 +38,22 @@ OUT = os.path.join(HERE, "csrc", "field_asm.inc")
 # SIMD (128 VGPRs each); the scratch takes the top of that budget.
 VBASE = 110
 MAX_WAYS = 3
-# Blocks written into the header (the others are built by render() and
-# checked by the CPU test; one- and two-product blocks measured slower than
-# the statement-level product, whose pieces the compiler interleaves with
-# other work).
-HEADER_WAYS = (3,)
+# Blocks written into the header: three products serve the four-lanes-per-
+# state layout (no wait state at all), one and two the one-word-per-lane
+# layout, whose lone waves pay for every wait state.  (The one-lane layout
+# keeps the statement-level product of field.hpp: its other waves hide the
+# wait states, and the compiler interleaves the pieces with other work.)
+HEADER_WAYS = (1, 2, 3)
 REGS_PER_PRODUCT = 6
 
 # One product as a list of instructions over symbolic registers:
 #   P, Z, U   scratch pairs (P.lo/P.hi, ... their halves)
-#   S         the product's SGPR pair (carries and borrows)
+#   S, T      the product's SGPR pairs (carries and borrows)
 #   AL AH BL BH   the 32-bit halves of the operands
 #   R         the output pair
 # Each step: (opcode, destination, carry destination, sources...).  Carry
-# destination "vcc" means the carry is not used.  A source of the form
-# "S" read as a carry-in is a hazard read of the SGPR pair S.
+# destination "vcc" means the carry is not used.  A last source "S" or "T"
+# of a carry reader is a hazard read of that SGPR pair.
 STEPS = [
     ("v_mad_u64_u32", "P", "vcc", "AL", "BL", "0"),        # p00 = a0 b0
     ("v_mov_b32", "Z.lo", None, "P.hi"),                    # Z = (hi(p00), 0)
@@ -63,16 +63,15 @@ STEPS = [
     ("v_mov_b32", "Z.lo", None, "U.hi"),                    # Z = (hi(u), 0)
     ("v_mad_u64_u32", "Z", "vcc", "AH", "BH", "Z"),        # h = a1 b1 + hi(u)
     ("v_subb_co_u32", "P.lo", "S", "P.lo", "Z.hi", "S"),   # y0 = lo(p00) - hi(h) - c
-    ("v_subb_co_u32", "P.hi", "S", "U.lo", "0", "S"),      # y1 = lo(u) - borrow
-    ("v_subb_co_u32", "U.hi", "vcc", "0", "0", "S"),       # m = -borrow
-    ("v_addc_co_u32", "P.lo", "S", "P.lo", "0", "S"),      # y += borrow * p:  y0 + borrow,
-    ("v_addc_co_u32", "P.hi", "vcc", "P.hi", "U.hi", "S"),  #              y1 + m + carry
-    ("v_mad_u64_u32", "U", "S", "Z.lo", "-1", "P"),        # r = lo(h) (2^32 - 1) + y, carry
-    ("v_addc_co_u32", "Z.hi", "vcc", "0", "0", "S"),       # k = carry
-    ("v_mad_u64_u32", "R", "vcc", "Z.hi", "-1", "U"),      # r + k (2^32 - 1), no carry
+    ("v_subb_co_u32", "P.hi", "S", "U.lo", "0", "S"),      # y1 = lo(u) - borrow; S = b
+    ("v_mad_u64_u32", "U", "T", "Z.lo", "-1", "P"),        # r1 + k 2^64 = lo(h) (2^32 - 1) + y
+    ("v_addc_co_u32", "Z.lo", "vcc", "0", "0", "T"),       # k
+    ("v_subb_co_u32", "Z.lo", "vcc", "Z.lo", "0", "S"),    # d = k - b, in {-1, 0, 1}
+    ("v_add_u32", "U.hi", None, "U.hi", "Z.lo"),            # r1 + d 2^32
+    ("v_mad_i64_i32", "R", "vcc", "Z.lo", "-1", "U"),      # - d (signed)
 ]
 
-# Instructions that read the SGPR pair S as a carry or borrow input.
+# Instructions that read an SGPR pair (S or T) as a carry or borrow input.
 CARRY_READERS = ("v_subb_co_u32", "v_addc_co_u32")
 HAZARD_WAIT = 2   # wait states between a VALU write of an SGPR and a VALU read of it
 
@@ -91,8 +90,8 @@ def scratch(k: int, reg: str) -> str:
 def operand(k: int, name: str, square: bool) -> str:
     if name in ("P", "Z", "U") or name[:2] in ("P.", "Z.", "U."):
         return scratch(k, name)
-    if name == "S":
-        return "%%[s%d]" % k
+    if name in ("S", "T"):
+        return "%%[%s%d]" % (name.lower(), k)
     if name == "R":
         return "%%[r%d]" % k
     if name in ("AL", "AH"):
@@ -109,18 +108,19 @@ def schedule(ways: int):
     (n wait states, printed as s_nop n-1)."""
     out = []
     pos = 0            # wait-state clock: an instruction is 1, "s_nop n-1" is n
-    last_write = {}    # product -> clock right after its last write of S
+    last_write = {}    # (product, pair) -> clock right after its last write
     for step in STEPS:
         for k in range(ways):
-            if step[0] in CARRY_READERS and step[-1] == "S" and k in last_write:
-                have = pos - last_write[k]
+            src = step[-1]
+            if step[0] in CARRY_READERS and src in ("S", "T") and (k, src) in last_write:
+                have = pos - last_write[(k, src)]
                 if have < HAZARD_WAIT:
                     out.append(("nop", HAZARD_WAIT - have))
                     pos += HAZARD_WAIT - have
             out.append(("insn", k, step))
             pos += 1
-            if step[2] == "S":
-                last_write[k] = pos
+            if step[2] in ("S", "T"):
+                last_write[(k, step[2])] = pos
     return out
 
 
@@ -149,17 +149,20 @@ def clobbers(ways: int):
 
 def function_text(ways: int, square: bool) -> str:
     name = "%s%d_asm" % ("sqr" if square else "mul", ways)
+    pairs = ("s", "t")
     params = []
     for k in range(ways):
         params.append("u64 a%d" % k)
         if not square:
             params.append("u64 b%d" % k)
     params += ["u64 &r%d" % k for k in range(ways)]
-    body = ["    u64 " + ", ".join("s%d" % k for k in range(ways)) + ";"]
+    body = ["    u64 " + ", ".join("%s%d" % (x, k) for x in pairs for k in range(ways)) + ";"]
+    lines = render(ways, square)
     asm = ["    asm volatile("]
-    asm += ['        "%s\\n\\t"' % line for line in render(ways, square)[:-1]]
-    asm.append('        "%s"' % render(ways, square)[-1])
-    outs = ['[r%d] "=v"(r%d)' % (k, k) for k in range(ways)] + ['[s%d] "=&s"(s%d)' % (k, k) for k in range(ways)]
+    asm += ['        "%s\\n\\t"' % line for line in lines[:-1]]
+    asm.append('        "%s"' % lines[-1])
+    outs = ['[r%d] "=v"(r%d)' % (k, k) for k in range(ways)]
+    outs += ['[%s%d] "=&s"(%s%d)' % (x, k, x, k) for x in pairs for k in range(ways)]
     ins = []
     for k in range(ways):
         ins += ['[a%dl] "v"(lo32(a%d))' % (k, k), '[a%dh] "v"(hi32(a%d))' % (k, k)]
@@ -175,8 +178,9 @@ def function_text(ways: int, square: bool) -> str:
 
 HEADER = """// Generated by paper_2506_09505_amd/gen_field_asm.py -- do not edit.
 //
-// Goldilocks products as single inline-assembly blocks interleaving three
-// independent products (see the generator for the sequence and why).
+// Goldilocks products as single inline-assembly blocks interleaving one, two
+// or three independent products (see the generator for the sequences and
+// why).
 // Scratch VGPRs v%d..v%d are declared clobbered.
 #pragma once
 

@@ -1,10 +1,10 @@
 """CPU checks of the generated product blocks (csrc/field_asm.inc, written by
-paper_2506_09505_amd/gen_field_asm.py).  The block text is executed here by a
-small interpreter of its five opcodes with exact integers, one lane at a
-time: every result must be congruent to the product mod p (Sec. 3.1,
-Eqs. 2-3), every carry must be read at least two wait states after the VALU
-instruction that wrote it, and the block may write only its outputs, its
-SGPR temporaries, VCC and the scratch VGPRs it declares clobbered."""
+paper_2506_09505_amd/gen_field_asm.py).  The block text is executed here by a small interpreter of its six opcodes with exact
+integers, one lane at a time: every result must be congruent to the product
+mod p (Sec. 3.1, Eqs. 2-3), every carry must be read at least two wait states
+after the VALU instruction that wrote it, and the block may write only its
+outputs, its SGPR temporaries, VCC and the scratch VGPRs it declares
+clobbered."""
 
 import random
 import re
@@ -64,7 +64,7 @@ class Lane:
         self.written.update((lo, hi))
 
     def sgpr(self, text):
-        m = re.fullmatch(r"%\[(s\d+)\]", text)
+        m = re.fullmatch(r"%\[([st]\d+)\]", text)
         assert m or text == "vcc", text
         return m.group(1) if m else "vcc"
 
@@ -92,6 +92,17 @@ class Lane:
                 val = self.read32(a) * self.read32(b) + self.read64(c)
                 self.write64(d, val)
                 self.write_carry(sd, val >> 64)
+            elif op == "v_mad_i64_i32":
+                d, sd, a, b, c = args
+                def s32(x):
+                    return x - (1 << 32) if x >> 31 else x
+                cv = self.read64(c)
+                cv = cv - (1 << 64) if cv >> 63 else cv
+                self.write64(d, s32(self.read32(a)) * s32(self.read32(b)) + cv)
+                self.write_carry(sd, 0)
+            elif op == "v_add_u32":
+                d, a, b = args
+                self.write32(d, self.read32(a) + self.read32(b))
             elif op == "v_mov_b32":
                 d, a = args
                 self.write32(d, self.read32(a))
@@ -128,11 +139,16 @@ EDGE = [0, 1, 2, M32 - 1, M32, M32 + 1, 2**63, P - 2, P - 1, P, P + 1, M64 - 1, 
         0xFFFFFFFF00000000, 0x00000001FFFFFFFF, 0xFFFFFFFEFFFFFFFF]
 
 
+# Operands whose product has lo(h) = 0, the case where the correction d is
+# -1 (a = s 2^48, b = t 2^48 with small s, t).
+LOW_H = [s << 48 for s in (1, 2, 3, 0xFFFF, 0x8000)]
+
+
 @pytest.mark.parametrize("ways", [1, 2, 3])
 @pytest.mark.parametrize("square", [False, True])
 def test_blocks_compute_products(ways, square):
     rnd = random.Random(ways * 7 + square)
-    cases = [(a, b) for a in EDGE for b in EDGE]
+    cases = [(a, b) for a in EDGE + LOW_H for b in EDGE + LOW_H]
     cases += [(rnd.getrandbits(64), rnd.getrandbits(64)) for _ in range(3000)]
     for i in range(0, len(cases) - ways + 1, ways):
         group = cases[i:i + ways]
@@ -143,9 +159,22 @@ def test_blocks_compute_products(ways, square):
             assert 0 <= r <= M64 and r % P == a * b % P, (ways, square, a, b)
 
 
-def test_three_way_block_needs_no_wait_states():
+def test_blocks_take_the_negative_correction():
+    # The d = -1 path (carry 0, borrow 1) must occur among the cases above.
+    seen = False
+    for a in LOW_H:
+        for b in LOW_H:
+            lane = Lane({"a0l": a & M32, "a0h": a >> 32, "b0l": b & M32, "b0h": b >> 32})
+            lane.run(gen.render(1, False))
+            d_reg = "v%d" % (gen.VBASE + 2)  # Z.lo holds d before the last fold
+            seen |= lane.v[d_reg] == M32
+    assert seen
+
+
+def test_wait_states_per_block():
     assert not any(line.startswith("s_nop") for line in gen.render(3, False))
-    assert sum(line.startswith("s_nop") for line in gen.render(1, False)) == 4
+    assert sum(line.startswith("s_nop") for line in gen.render(2, False)) == 2
+    assert sum(line.startswith("s_nop") for line in gen.render(1, False)) == 2
 
 
 def test_a_planted_mistake_is_caught():
@@ -156,7 +185,9 @@ def test_a_planted_mistake_is_caught():
     with pytest.raises(AssertionError):
         lane.run(lines)
     lines = gen.render(1, False)
-    dropped = [l for l in lines if not l.startswith("v_addc_co_u32 v113")]
+    target = "v_addc_co_u32 v112"
+    assert sum(l.startswith(target) for l in lines) == 1
+    dropped = [l for l in lines if not l.startswith(target)]
     a = b = M64
     lane = Lane({"a0l": a & M32, "a0h": a >> 32, "b0l": b & M32, "b0h": b >> 32})
     lane.run(dropped)

@@ -29,8 +29,8 @@ def mad_eps_fold(h, x):
 
 def mul_fold(a, b):
     """The product with the middle carry folded into the reduction and the
-    borrow fixed up before the final fold: the sequence of the generated
-    three-product blocks (field_asm.inc)."""
+    borrow fixed up (p added) before the final fold: the earlier sequence of
+    the generated blocks, kept as a second derivation of the same residue."""
     a0, a1, b0, b1 = a & M32, a >> 32, b & M32, b >> 32
     p00, c0 = mad(a0, b0, 0)
     t, c1 = mad(a1, b0, p00 >> 32)
