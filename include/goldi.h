@@ -145,7 +145,7 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
  *   "quad_max_parents" tree levels of at most this many parents do the same
  *                      (default 2^16);
  *   "lane12_max_rows", "lane12_max_parents"
- *                      at or below these sizes (defaults 2^13 and 2^12) one
+ *                      at or below these sizes (default 2^13 each) one
  *                      state word per lane (a 16-lane row per state) is used
  *                      instead: lower latency again, ~3x the instructions
  *                      per row;

@@ -41,7 +41,7 @@ def signature(shapes) -> str:
 def candidates():
     for bm, gr in ((0, 0), (1, 0), (1, 1)):
         for qr, qp in itertools.product((1 << 14, 1 << 16), (1 << 16, 1 << 17)):
-            for l12_rows, l12_par in ((1 << 10, 1 << 10), (1 << 12, 1 << 12), (1 << 13, 1 << 12)):
+            for l12_rows, l12_par in ((1 << 10, 1 << 10), (1 << 12, 1 << 12), (1 << 13, 1 << 13)):
                 yield {"batch_mode": bm, "graph": gr, "quad_max_rows": qr, "quad_max_parents": qp,
                        "lane12_max_rows": l12_rows, "lane12_max_parents": l12_par}
 

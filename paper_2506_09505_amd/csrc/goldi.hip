@@ -229,7 +229,7 @@ std::atomic<size_t> g_graph_mode{env_size("GOLDI_GRAPH_MODE", 0)};
 // At or below these sizes the one-word-per-lane kernels run instead (lower
 // latency still, more instructions in total).
 std::atomic<size_t> g_l12_max_rows{env_size("GOLDI_LANE12_MAX_ROWS", (size_t)1 << 13)};
-std::atomic<size_t> g_l12_max_parents{env_size("GOLDI_LANE12_MAX_PARENTS", (size_t)1 << 12)};
+std::atomic<size_t> g_l12_max_parents{env_size("GOLDI_LANE12_MAX_PARENTS", (size_t)1 << 13)};
 // Single-tree builds finish in one single-workgroup launch (k_levels_lane12)
 // from the first level of at most this many parents (<= 64; the default 16
 // keeps one wave per SIMD of the workgroup's CU); 0 disables.
@@ -431,13 +431,10 @@ int launch_split(const uint64_t *leaves, size_t n_rows, size_t n_cols, uint64_t 
         size_t off = 0, n = n_rows;
         for (size_t L = 0; L < depth && rc == GOLDI_OK;) {
             const size_t c0 = b[k] >> L, c1 = k + 1 < parts ? b[k + 1] >> L : n;
-            // Latency-bound levels (one word per lane) are sized by the part's
-            // own parents: each part's launch is one permutation latency
-            // however wide its neighbour is.  The one-lane versus four-lane
-            // choice follows the whole level's width: those launches run side
-            // by side and share the GPU like one launch.
+            // Every layout choice follows the whole level's width: the parts'
+            // launches run side by side and share the GPU like one launch.
             size_t done = 1;
-            if ((c1 - c0 + 1) / 2 <= l12_max_parents()) {
+            if ((n + 1) / 2 <= l12_max_parents()) {
                 done = std::min((size_t)kLevelsPerLaunch, depth - L);  // c0, c1: multiples of 2^(depth - L)
                 rc = launch_levels_lane12(nodes, off, n, c0, c1, (int)done, sk);
             } else {

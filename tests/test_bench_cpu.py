@@ -30,7 +30,7 @@ def test_work_count():
 
 class _Knobs:
     def __init__(self, **kw):
-        self.v = dict(lane12_max_rows=1 << 13, quad_max_rows=1 << 14, lane12_max_parents=1 << 12,
+        self.v = dict(lane12_max_rows=1 << 13, quad_max_rows=1 << 14, lane12_max_parents=1 << 13,
                       quad_max_parents=1 << 16, top_max_parents=16)
         self.v.update(kw)
 
@@ -41,12 +41,12 @@ class _Knobs:
 def test_schedule_of_the_paper_scale_tree():
     perms, launches = bench.schedule(_Knobs(), 1 << 22, 8)
     assert sum(perms.values()) == bench.perms_per_build(1 << 22, 8)
-    # levels of 2^12 .. 2^8 parents in one launch, then 2^7 .. 2^3, then 4 .. 1
+    # levels of 2^13 .. 2^9 parents in one launch, then 2^8 .. 2^4, then 8 .. 1
     assert launches == {"leaf_hash": 1, "leaf_hash_quad": 0, "leaf_hash_lane12": 0, "level": 5,
-                        "level_quad": 4, "levels_lane12": 2, "top_lane12": 1}
+                        "level_quad": 3, "levels_lane12": 2, "top_lane12": 1}
     assert perms["level"] == sum(1 << k for k in range(17, 22))
-    assert perms["levels_lane12"] == sum(1 << k for k in range(3, 13))
-    assert perms["top_lane12"] == 4 + 2 + 1
+    assert perms["levels_lane12"] == sum(1 << k for k in range(4, 14))
+    assert perms["top_lane12"] == 8 + 4 + 2 + 1
 
 
 def test_schedule_ragged_and_tiny():
