@@ -59,6 +59,19 @@ __device__ __forceinline__ u64 sbox(u64 x) {
     return mul(x4, x3);
 }
 
+// One S-box with its four products as asm blocks (field_asm.inc): x^2
+// alone, x^3 and x^4 interleaved, x^7 alone.  Where few waves share a SIMD
+// (the narrow layouts' single S-boxes) this spends only the wait states each
+// carry read needs: 2 per block, against about 7 per statement-level product,
+// whose asm statements the compiler pads.
+__device__ __forceinline__ u64 sbox_blocks(u64 x) {
+    u64 x2, x3, x4, x7;
+    sqr1_asm(x, x2);
+    mul2_asm(x2, x, x2, x2, x3, x4);
+    mul1_asm(x4, x3, x7);
+    return x7;
+}
+
 // Three independent S-boxes, each stage as one block of three interleaved
 // products (field_asm.inc): no wait state is spent on a carry.  Measured on
 // MI355X this helps where a lane holds three words and few waves share a

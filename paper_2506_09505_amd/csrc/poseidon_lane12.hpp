@@ -103,18 +103,6 @@ __device__ __forceinline__ Lane12 lane12_setup(const QuadRc &) {
     return L;
 }
 
-// The S-box with its four products as asm blocks (field_asm.inc): x^2
-// alone, x^3 and x^4 interleaved, x^7 alone.  A lone wave then spends only
-// the wait states each carry read needs (2 per block, against about 7 per
-// statement-level product, whose asm statements the compiler pads).
-__device__ __forceinline__ u64 sbox_blocks(u64 x) {
-    u64 x2, x3, x4, x7;
-    sqr1_asm(x, x2);
-    mul2_asm(x2, x, x2, x2, x3, x4);
-    mul1_asm(x4, x3, x7);
-    return x7;
-}
-
 // Word J of this lane's 16-lane row, in every lane of the row.
 template <int J>
 __device__ __forceinline__ u64 row_bcast(u64 v) {

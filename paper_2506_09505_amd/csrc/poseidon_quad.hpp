@@ -86,7 +86,7 @@ __device__ __forceinline__ void quad_partial_round(u64 w[3], const u64 (*rc_lane
     u64 masked[3] = {mk64(lo32(w0) & nz, hi32(w0) & nz), w[1], w[2]};
     u64 a_lo[3], a_hi[3];
     quad_mds_accumulate(masked, rc_lane, a_lo, a_hi);
-    const u64 sb = sbox(w0);
+    const u64 sb = sbox_blocks(w0);
     const u32 s_lo = (u32)__builtin_amdgcn_mov_dpp((int)lo32(sb), 0x00, 0xF, 0xF, false);  // quad_perm [0,0,0,0]
     const u32 s_hi = (u32)__builtin_amdgcn_mov_dpp((int)hi32(sb), 0x00, 0xF, 0xF, false);
 #pragma unroll
@@ -179,7 +179,7 @@ __device__ __forceinline__ void quad_chain(u64 (&s)[GOLDI_BLK], const u64 (&p_lo
     if constexpr (M < GOLDI_BLK) {
         u64 a_lo = p_lo[M - 1], a_hi = p_hi[M - 1];
         quad_chain_sterms<M>(s, a_lo, a_hi);
-        s[M] = sbox(reduce_split(a_lo, a_hi));
+        s[M] = sbox_blocks(reduce_split(a_lo, a_hi));
         quad_chain<M + 1>(s, p_lo, p_hi);
     }
 }
@@ -195,7 +195,7 @@ __device__ __forceinline__ void quad_block(u64 w[3], int q, const QuadBlk &qb, i
         x[3][k] = quad_fetch64<3>(w[k]);
     }
     u64 s[GOLDI_BLK];
-    s[0] = sbox(w[0]);  // the block's first S-box (lane 0's word 0)
+    s[0] = sbox_blocks(w[0]);  // the block's first S-box (lane 0's word 0)
     // This lane's share of the chain rows, then the sum over the quad.
     u64 p_lo[GOLDI_BLK - 1], p_hi[GOLDI_BLK - 1];
 #pragma unroll
