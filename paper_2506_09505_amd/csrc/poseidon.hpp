@@ -108,6 +108,14 @@ __device__ __forceinline__ u64 reduce_split(u64 a_lo, u64 a_hi) {
     return out;
 }
 
+// reduce_split as compiler-visible code, for the narrow layouts (see
+// mad_small_c: no padding after asm statements).
+__device__ __forceinline__ u64 reduce_split_c(u64 a_lo, u64 a_hi) {
+    const u64 r = mad32(hi32(a_hi), 0xFFFFFFFFu, a_lo);
+    const u64 s_hi = (u64)hi32(r) + lo32(a_hi);
+    return mad32((u32)(s_hi >> 32), 0xFFFFFFFFu, mk64(lo32(r), (u32)s_hi));
+}
+
 // m * x + acc for a matrix entry m (an inline constant, 1..64) as exactly
 // one v_mad_u64_u32; left to itself the compiler turns some entries (powers
 // of two) into longer shift-and-mask sequences on the 64-bit pair.
@@ -125,6 +133,25 @@ __device__ __forceinline__ u64 mad_small(u32 x, u64 acc) {
         u64 r;
         asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(r) : "v"(x), "i"(M), "v"(acc) : "vcc");
         return r;
+    }
+}
+
+// m * x + acc as compiler-visible code, for the narrow layouts: the compiler
+// pads each inline-asm statement before a dependent read (it cannot rule out
+// a transcendental instruction inside), which costs where few waves share a
+// SIMD.  A power-of-two entry goes through an opaque scalar register, so that
+// it stays one v_mad_u64_u32 instead of a shift sequence.
+template <unsigned M>
+__device__ __forceinline__ u64 mad_small_c(u32 x, u64 acc) {
+    static_assert(M <= 64, "matrix entries are inline constants");
+    if constexpr (M == 0) {
+        return acc;
+    } else if constexpr ((M & (M - 1)) != 0) {
+        return mad32(x, M, acc);
+    } else {
+        u32 m;
+        asm("" : "=s"(m) : "0"(M));
+        return mad32(x, m, acc);
     }
 }
 

@@ -124,7 +124,7 @@ __device__ __forceinline__ u64 lane12_full(u64 x, const u32 (&c)[WIDTH], const u
     const u64 s = sbox_blocks(x);
     u64 a_lo = k[0], a_hi = k[1];
     row_terms<0, WIDTH>(s, c, a_lo, a_hi);
-    return reduce_split(a_lo, a_hi);
+    return reduce_split_c(a_lo, a_hi);
 }
 
 // Partial round: word 0's S-box runs while the other words' terms add up;
@@ -136,7 +136,7 @@ __device__ __forceinline__ u64 lane12_partial(u64 x, const u32 (&c)[WIDTH], cons
     const u64 sb = row_bcast<0>(s);
     a_lo = mad32(c[0], lo32(sb), a_lo);
     a_hi = mad32(c[0], hi32(sb), a_hi);
-    return reduce_split(a_lo, a_hi);
+    return reduce_split_c(a_lo, a_hi);
 }
 
 #if GOLDI_USE_BLOCKS
@@ -148,10 +148,10 @@ __device__ __forceinline__ u64 lane12_lead(u64 x, const Lane12 &L, const u32 (&c
     const u64 s = sbox_blocks(x);
     u64 a_lo = k[0], a_hi = k[1];
     row_terms<0, WIDTH>(s, c, a_lo, a_hi);
-    const u64 su = row_bcast<WIDTH>(sbox_blocks(reduce_split(a_lo, a_hi)));
+    const u64 su = row_bcast<WIDTH>(sbox_blocks(reduce_split_c(a_lo, a_hi)));
     a_lo = mad32(L.f_lead, lo32(su), a_lo);
     a_hi = mad32(L.f_lead, hi32(su), a_hi);
-    return reduce_split(a_lo, a_hi);
+    return reduce_split_c(a_lo, a_hi);
 }
 
 // S-box outputs M .. GOLDI_BLK-1 of the block: the S-box input of round M
@@ -159,7 +159,7 @@ __device__ __forceinline__ u64 lane12_lead(u64 x, const Lane12 &L, const u32 (&c
 template <int M>
 __device__ __forceinline__ void lane12_chain(const Lane12 &L, u64 &a_lo, u64 &a_hi) {
     if constexpr (M < GOLDI_BLK) {
-        const u64 sb = row_bcast<WIDTH + M - 1>(sbox_blocks(reduce_split(a_lo, a_hi)));
+        const u64 sb = row_bcast<WIDTH + M - 1>(sbox_blocks(reduce_split_c(a_lo, a_hi)));
         a_lo = mad32(L.f[M], lo32(sb), a_lo);
         a_hi = mad32(L.f[M], hi32(sb), a_hi);
         lane12_chain<M + 1>(L, a_lo, a_hi);
@@ -176,7 +176,7 @@ __device__ __forceinline__ u64 lane12_block(u64 x, const Lane12 &L, const u64 (&
     a_lo = mad32(L.f[0], lo32(sb), a_lo);
     a_hi = mad32(L.f[0], hi32(sb), a_hi);
     lane12_chain<1>(L, a_lo, a_hi);
-    return reduce_split(a_lo, a_hi);
+    return reduce_split_c(a_lo, a_hi);
 }
 #endif
 

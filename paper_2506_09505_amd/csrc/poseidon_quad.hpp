@@ -38,8 +38,8 @@ __device__ __forceinline__ u64 quad_fetch64(u64 v) {
 template <int R, int D, int K>
 __device__ __forceinline__ void quad_row_terms(const u64 (&x)[4][3], u64 &a_lo, u64 &a_hi) {
     constexpr unsigned m = GOLDI_MDS[0][(3 * D + K - R + 12) % 12];
-    a_lo = mad_small<m>(lo32(x[D][K]), a_lo);
-    a_hi = mad_small<m>(hi32(x[D][K]), a_hi);
+    a_lo = mad_small_c<m>(lo32(x[D][K]), a_lo);
+    a_hi = mad_small_c<m>(hi32(x[D][K]), a_hi);
     if constexpr (K < 2) {
         quad_row_terms<R, D, K + 1>(x, a_lo, a_hi);
     } else if constexpr (D < 3) {
@@ -73,7 +73,7 @@ __device__ __forceinline__ void quad_mds_add_rc(u64 w[3], const u64 (*rc_lane)[2
     u64 a_lo[3], a_hi[3];
     quad_mds_accumulate(w, rc_lane, a_lo, a_hi);
 #pragma unroll
-    for (int r = 0; r < 3; r++) w[r] = reduce_split(a_lo[r], a_hi[r]);
+    for (int r = 0; r < 3; r++) w[r] = reduce_split_c(a_lo[r], a_hi[r]);
 }
 
 // Partial round, arranged so the matrix product does not wait for the S-box:
@@ -93,7 +93,7 @@ __device__ __forceinline__ void quad_partial_round(u64 w[3], const u64 (*rc_lane
     for (int r = 0; r < 3; r++) {
         a_lo[r] = mad32(m0[r], s_lo, a_lo[r]);
         a_hi[r] = mad32(m0[r], s_hi, a_hi[r]);
-        w[r] = reduce_split(a_lo[r], a_hi[r]);
+        w[r] = reduce_split_c(a_lo[r], a_hi[r]);
     }
 }
 
@@ -179,7 +179,7 @@ __device__ __forceinline__ void quad_chain(u64 (&s)[GOLDI_BLK], const u64 (&p_lo
     if constexpr (M < GOLDI_BLK) {
         u64 a_lo = p_lo[M - 1], a_hi = p_hi[M - 1];
         quad_chain_sterms<M>(s, a_lo, a_hi);
-        s[M] = sbox_blocks(reduce_split(a_lo, a_hi));
+        s[M] = sbox_blocks(reduce_split_c(a_lo, a_hi));
         quad_chain<M + 1>(s, p_lo, p_hi);
     }
 }
@@ -237,7 +237,7 @@ __device__ __forceinline__ void quad_block(u64 w[3], int q, const QuadBlk &qb, i
             a_lo[r] = mad32(qb.f[q][r][m], lo32(s[m]), a_lo[r]);
             a_hi[r] = mad32(qb.f[q][r][m], hi32(s[m]), a_hi[r]);
         }
-        w[r] = reduce_split(a_lo[r], a_hi[r]);
+        w[r] = reduce_split_c(a_lo[r], a_hi[r]);
     }
 }
 #endif
