@@ -688,7 +688,7 @@ def bench_functions(args) -> int:
 
     from paper_2506_09505_amd import count_valu, fieldbench
     torch.cuda.set_device(0)
-    valu = count_valu.read()  # written by the build from this build's own code object
+    valu = count_valu.read()  # written at build time from the library's own code object
     rows = {}
     for name in fieldbench.OPS:
         iters = 8 if name == "mmult_12x12_full" else 64

@@ -322,7 +322,7 @@ def goldi_tune_set(key: str, value: int) -> None:
 
 def goldi_tune_get(key: str) -> int:
     """Current value of a schedule knob, or of the read-only "partial_form"
-    (how this build evaluates the partial rounds: 2 blocks, 1 sparse, 0 dense)."""
+    (how the loaded library evaluates the partial rounds: 2 blocks, 1 sparse, 0 dense)."""
     v = ctypes.c_size_t()
     _check(lib().goldi_tune_get(key.encode(), ctypes.byref(v)), "goldi_tune_get")
     return v.value

@@ -64,7 +64,7 @@ def write(asm_path: str) -> dict:
         counts = counts_from_asm(f.read())
     with open(OUT, "w") as f:
         json.dump({"valu_per_call": counts,
-                   "source": "innermost loop of k_fb_chain<op> in this build's gfx950 assembly "
+                   "source": "innermost loop of k_fb_chain<op> in the library's gfx950 assembly "
                              "(paper_2506_09505_amd/count_valu.py), per call"}, f, indent=1)
     return counts
 

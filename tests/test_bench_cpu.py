@@ -87,7 +87,7 @@ def test_profile_records_follow_the_sources(tmp_path, monkeypatch):
 
 
 def test_function_instruction_counts_from_the_build():
-    # The Table-1 instruction counts come from this build's own code object
+    # The Table-1 instruction counts come from the library's own code object
     # (count_valu.py, run by the build): every function is counted, and the
     # parser takes the innermost loop of each chain kernel.
     from paper_2506_09505_amd import count_valu
