@@ -18,7 +18,8 @@
 // (0, 12, 13) and added in with the lane's f coefficient.  The first partial
 // round rides on the last opening round: lanes 0..11 take the rows of M P M,
 // lane 12 row 0 of M, whose result is that partial round's S-box input.
-// Lanes 14 and 15 follow along with copies of lane 0's rows.
+// Lanes 14 and 15 only follow along: their rows copy a helper lane's, and
+// nothing reads their results.
 #pragma once
 #include "poseidon_quad.hpp"
 
