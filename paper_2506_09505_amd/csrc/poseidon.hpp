@@ -556,15 +556,32 @@ __device__ __forceinline__ void lead_matrix(const u64 y[WIDTH], u64 out[WIDTH]) 
     lead_rows<0>(y, sbox(u[0]), out);
 }
 
-__device__ __forceinline__ void partial_block(u64 s[WIDTH], int b) {
+// Block b from state s into out (every row reads all of s, so the two
+// cannot share registers).
+__device__ __forceinline__ void partial_block_to(const u64 s[WIDTH], u64 out[WIDTH], int b) {
     const u64 (*kc)[2] = BLK_K[b];
     u64 x[GOLDI_BLK];
     x[0] = sbox(s[0]);
     blk_chain<1>(s, x, kc);
-    u64 out[WIDTH];
     blk_rows<0>(s, x, out, kc + GOLDI_BLK - 1);
+}
+
+// All blocks, in place.  Two blocks per loop step, the second writing back
+// into s, so the state is not copied between blocks: with one block per
+// step, the loop-carried outputs cannot take the inputs' registers and each
+// step ends with a 12-word copy (measured: -1% on the 2^22 x 8 tree).
+__device__ __forceinline__ void partial_blocks(u64 s[WIDTH]) {
+    u64 t[WIDTH];
+#pragma nounroll
+    for (int b = 0; b + 1 < GOLDI_BLK_N; b += 2) {
+        partial_block_to(s, t, b);
+        partial_block_to(t, s, b + 1);
+    }
+    if constexpr (GOLDI_BLK_N % 2 == 1) {
+        partial_block_to(s, t, GOLDI_BLK_N - 1);
 #pragma unroll
-    for (int i = 0; i < WIDTH; i++) s[i] = out[i];
+        for (int i = 0; i < WIDTH; i++) s[i] = t[i];
+    }
 }
 #endif
 
@@ -609,8 +626,7 @@ __device__ __forceinline__ void permute(u64 s[WIDTH], bool cap0 = false, bool di
         for (int i = 0; i < WIDTH; i++) s[i] = out[i];
     }
 #if GOLDI_USE_BLOCKS
-#pragma nounroll
-    for (int b = 0; b < GOLDI_BLK_N; b++) partial_block(s, b);
+    partial_blocks(s);
 #pragma unroll
     for (int r = GOLDI_BLK_FIRST_TAIL; r < HALF_FULL + PARTIAL; r++) partial_round(s, r);
 #elif GOLDI_USE_SPARSE
