@@ -156,7 +156,7 @@ int goldi_merkle_build_many_noalloc(const goldi_tree_t *trees, size_t n_trees, i
  *   "split_parts"      single-tree builds of at least "split_min_rows" rows
  *                      (default 2^20) hash the leaves and build every level
  *                      with more than "split_join_parents" parents (default
- *                      16) as this many ranges of rows (default 2, at most 4;
+ *                      4096) as this many ranges of rows (default 2, at most 4;
  *                      0 or 1 = no split), each on its own library-owned
  *                      stream (created on first use per device, default
  *                      priority), joined on the caller's stream before the

@@ -341,8 +341,8 @@ int launch_upper(uint64_t *nodes, size_t off, size_t n, hipStream_t st) {
 // hold fewer and fewer waves, and the other stream's launch fills them; and
 // a latency-bound level (a few thousand parents or fewer) costs about one
 // permutation latency whatever its width, so two half-width launches side by
-// side take the time of one.  Three and four parts, and unequal halves,
-// measured slower.  Part k covers leaves [b_k, b_(k+1)); every boundary is a
+// side take the time of one.  Three and four parts, and unequal halves (the
+// caller's part 1/64 .. 1/256 larger or smaller), measured slower.  Part k covers leaves [b_k, b_(k+1)); every boundary is a
 // multiple of 2^depth, so at each of the first `depth` levels part k's nodes
 // are [b_k >> L, b_(k+1) >> L) of level L and every part but the last has an
 // even number of children.  The nodes written are the same as an unsplit
@@ -357,7 +357,7 @@ struct NoSplitScope {
     ~NoSplitScope() { t_no_split = old; }
 };
 std::atomic<size_t> g_split_min_rows{env_size("GOLDI_SPLIT_MIN_ROWS", (size_t)1 << 20)};
-std::atomic<size_t> g_split_join_parents{env_size("GOLDI_SPLIT_JOIN_PARENTS", 16)};
+std::atomic<size_t> g_split_join_parents{env_size("GOLDI_SPLIT_JOIN_PARENTS", 4096)};
 constexpr size_t kMaxSplit = 4;
 
 // Library-owned streams (default priority, non-blocking) for parts 1.., one
